@@ -1,0 +1,183 @@
+"""Seeded synthetic scenes: tetrahedral meshes, materials and Dirichlet schedules.
+
+This module only generates inputs.  It holds none of the method's arithmetic
+(no energies, derivatives, projections or solves), so both the CPU oracle and
+the GPU library take their scenes from here.
+
+Meshes are regular grids of hexahedral cells, each split into six tetrahedra
+along the cell diagonal (0,0,0)->(1,1,1) (the Kuhn / Freudenthal split).  The
+six tetrahedra of a cell are the six monotone lattice paths from the cell's
+low corner to its high corner, one per permutation of the three axes.  For an
+odd permutation the second and third vertices are swapped, which makes every
+tetrahedron positively oriented; the orientation follows from the parity of
+the permutation alone, so no determinant is evaluated here.
+
+Parameter ranges follow the paper's scene table (Sec. 5.1, Table 1):
+Young's modulus 1e4..1e6 Pa, Poisson ratio 0.40..0.49, density 1000 kg/m^3,
+time steps 1/30 and 1/60 s.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+from typing import Callable
+
+import numpy as np
+
+GRAVITY = (0.0, 0.0, -9.81)
+
+# Permutations of the axes in lexicographic order, with their parity.
+_PERMS = list(itertools.permutations((0, 1, 2)))
+_ODD = {(0, 2, 1), (1, 0, 2), (2, 1, 0)}
+
+
+def kuhn_grid(nx: int, ny: int, nz: int, size=(1.0, 1.0, 1.0)):
+    """Vertices (N,3) float64 and tetrahedra (T,4) int32 of an nx*ny*nz grid.
+
+    Vertex id = (i*(ny+1) + j)*(nz+1) + k; cells in lexicographic (i, j, k)
+    order; six tetrahedra per cell in permutation order.
+    """
+    nvx, nvy, nvz = nx + 1, ny + 1, nz + 1
+    ii, jj, kk = np.meshgrid(np.arange(nvx), np.arange(nvy), np.arange(nvz), indexing="ij")
+    X = np.stack([ii.ravel() * (size[0] / nx),
+                  jj.ravel() * (size[1] / ny),
+                  kk.ravel() * (size[2] / nz)], axis=1).astype(np.float64)
+
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+
+    def vid(di, dj, dk):
+        return ((ci + di) * nvy + (cj + dj)) * nvz + (ck + dk)
+
+    tets = np.empty((ci.size, 6, 4), dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        off = [0, 0, 0]
+        path = [vid(*off)]
+        for ax in perm:
+            off[ax] += 1
+            path.append(vid(*off))
+        if perm in _ODD:
+            path[1], path[2] = path[2], path[1]
+        tets[:, p, :] = np.stack(path, axis=1)
+    return X, tets.reshape(-1, 4).astype(np.int32)
+
+
+@dataclass
+class Scene:
+    """Everything one simulation run needs, independent of the solver."""
+    name: str
+    X: np.ndarray                 # rest positions (N,3) [m]
+    tets: np.ndarray              # (T,4) int32
+    x0: np.ndarray                # initial positions (N,3)
+    v0: np.ndarray                # initial velocities (N,3)
+    E: np.ndarray                 # Young's modulus per element (T,) [Pa]
+    nu: np.ndarray                # Poisson ratio per element (T,)
+    rho: float                    # density [kg/m^3]
+    dt: float                     # time step [s]
+    gravity: tuple
+    dirichlet_ids: np.ndarray     # (n_D,) int32, ascending
+    targets: Callable[[int], np.ndarray] = field(repr=False)  # step n -> (n_D,3) targets at t_n
+    n_steps: int = 1
+    stop_mode: str = "vel"        # "vel": dt^-1 |dx|_inf < tol ; "grad_rel": |g|_2 <= tol |g0|_2
+    stop_tol: float = 1e-3
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_verts(self) -> int:
+        return self.X.shape[0]
+
+    @property
+    def n_tets(self) -> int:
+        return self.tets.shape[0]
+
+
+def _face(X, axis, value, atol=1e-12):
+    return np.nonzero(np.abs(X[:, axis] - value) <= atol)[0].astype(np.int32)
+
+
+def cube_jitter(n=6, E=1e5, nu=0.45, rho=1000.0, dt=1.0 / 60.0, jitter=0.05, seed=0,
+                n_steps=20) -> Scene:
+    """Small parity scene: unit cube of n^3 cells, bottom face pinned to rest,
+    gravity, every initial vertex jittered by U(-jitter*cell, +jitter*cell)."""
+    X, tets = kuhn_grid(n, n, n)
+    cell = 1.0 / n
+    rng = np.random.default_rng(seed)
+    x0 = X + rng.uniform(-jitter * cell, jitter * cell, size=X.shape)
+    ids = _face(X, 2, 0.0)
+    tgt = X[ids].copy()
+    T = tets.shape[0]
+    return Scene(name=f"cube{n}_jitter", X=X, tets=tets, x0=x0, v0=np.zeros_like(X),
+                 E=np.full(T, E), nu=np.full(T, nu), rho=rho, dt=dt, gravity=GRAVITY,
+                 dirichlet_ids=ids, targets=lambda step: tgt, n_steps=n_steps,
+                 stop_mode="grad_rel", stop_tol=1e-6,
+                 meta=dict(cells=(n, n, n), size=(1.0, 1.0, 1.0)))
+
+
+def beam_twist(nx=80, ny=16, nz=16, L=1.0, W=0.2, E=1e5, nu=0.45, rho=1000.0, dt=1.0 / 30.0,
+               turns=2.0, n_steps=100) -> Scene:
+    """Beam fixed at x = 0; the x = L face is driven to c + R_x(theta_n)(X - c)
+    with theta_n = 2*pi*turns*n/n_steps (c = face centre)."""
+    X, tets = kuhn_grid(nx, ny, nz, size=(L, W, W))
+    left = _face(X, 0, 0.0)
+    right = _face(X, 0, L)
+    ids = np.concatenate([left, right]).astype(np.int32)
+    order = np.argsort(ids, kind="stable")
+    ids = ids[order]
+    base = X[ids].copy()
+    is_right = np.isin(ids, right)
+    c = np.array([L, W / 2, W / 2])
+
+    def targets(step):
+        th = 2.0 * math.pi * turns * step / n_steps
+        ct, st = math.cos(th), math.sin(th)
+        t = base.copy()
+        r = base[is_right] - c
+        t[is_right, 1] = c[1] + ct * r[:, 1] - st * r[:, 2]
+        t[is_right, 2] = c[2] + st * r[:, 1] + ct * r[:, 2]
+        return t
+
+    T = tets.shape[0]
+    return Scene(name=f"beam{nx}x{ny}x{nz}_twist", X=X, tets=tets, x0=X.copy(),
+                 v0=np.zeros_like(X), E=np.full(T, E), nu=np.full(T, nu), rho=rho, dt=dt,
+                 gravity=GRAVITY, dirichlet_ids=ids, targets=targets, n_steps=n_steps,
+                 stop_mode="vel", stop_tol=1e-3,
+                 meta=dict(cells=(nx, ny, nz), size=(L, W, W)))
+
+
+def cube_compress(n=64, L=1.0, E_lo=1e4, E_hi=1e6, nu=0.48, rho=1000.0, dt=1.0 / 30.0,
+                  squash=0.6, ramp_steps=50, n_steps=50, seed=2) -> Scene:
+    """Cube pinned at z = 0; the top face is driven to (X, Y, L(1 - squash*min(1, n/ramp)))
+    while E is drawn log-uniformly per element."""
+    X, tets = kuhn_grid(n, n, n, size=(L, L, L))
+    rng = np.random.default_rng(seed)
+    T = tets.shape[0]
+    E = np.exp(rng.uniform(math.log(E_lo), math.log(E_hi), size=T))
+    bot = _face(X, 2, 0.0)
+    top = _face(X, 2, L)
+    ids = np.sort(np.concatenate([bot, top])).astype(np.int32)
+    base = X[ids].copy()
+    is_top = np.isin(ids, top)
+
+    def targets(step):
+        t = base.copy()
+        t[is_top, 2] = L * (1.0 - squash * min(1.0, step / ramp_steps))
+        return t
+
+    return Scene(name=f"cube{n}_compress", X=X, tets=tets, x0=X.copy(), v0=np.zeros_like(X),
+                 E=E, nu=np.full(T, nu), rho=rho, dt=dt, gravity=GRAVITY,
+                 dirichlet_ids=ids, targets=targets, n_steps=n_steps,
+                 stop_mode="vel", stop_tol=1e-3,
+                 meta=dict(cells=(n, n, n), size=(L, L, L)))
+
+
+def config(k: int, **kw) -> Scene:
+    """The workload configurations by index: 0 small parity cube, 1 twisted
+    beam (122,880 tets), 2 compressed heterogeneous cube (1,572,864 tets)."""
+    if k == 0:
+        return cube_jitter(**kw)
+    if k == 1:
+        return beam_twist(**kw)
+    if k == 2:
+        return cube_compress(**kw)
+    raise ValueError(f"unknown configuration {k}")
