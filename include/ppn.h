@@ -1,0 +1,245 @@
+/*
+ * ppn.h -- C ABI of the MI355X (gfx950) implementation of Progressively
+ * Projected Newton (PPN) for implicit hyperelastic time stepping on linear
+ * tetrahedra, with Projected Newton (PN) and Project-on-Demand Newton (PDN)
+ * as comparison modes (arXiv 2505.21013).
+ *
+ * One time step is the minimisation of the backward-Euler incremental
+ * potential (Sec. 3, Eq. (1); Sec. 5.1 "Time stepping and tolerances")
+ *     Psi(x) = sum_i m_i/(2h^2)|x_i - xhat_i|^2 + sum_e V_e psi(F_e)
+ *              + sum_{i in D} k_D/2 |x_i - xbar_i|^2
+ * by Newton's method, where psi is the Stable Neo-Hookean energy
+ *     psi(F) = mu/2 (tr F^T F - 3) - mu (J - 1) + lam/2 (J - 1)^2
+ * with mu = mu_L, lam = lam_L + mu_L from (E, nu) (Sec. 5.1, material model),
+ * lumped masses m_i = sum_{e ni i} rho V_e/4, xhat = x^n + h v^n + h^2 g_grav
+ * and Dirichlet constraints as penalty potentials (Sec. 5.1).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are HOST memory unless the parameter name ends in "_dev".
+ *    Inputs are copied during the call; the caller keeps ownership.
+ *  - The library owns all of its device memory (hipMalloc at load time).
+ *  - Vectors of points are AoS, [n][3] doubles (x0 y0 z0 x1 ...).
+ *  - Every function returns a ppn_status: negative = error, nothing changed;
+ *    positive = warning, the state did advance.  No exception crosses the
+ *    ABI; ppn_last_error() gives the message of the last failing call.
+ *  - A scene handle is used by one host thread at a time and is bound to the
+ *    HIP stream given at creation (NULL = a stream the library creates).
+ *    Calls are synchronous with respect to that stream: on return, results
+ *    are final.
+ */
+#ifndef PPN_H
+#define PPN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ppn_scene ppn_scene; /* opaque, library-owned */
+
+/* Newton variants.  PN: project every element Hessian (Sec. 3).  PDN: project
+ * all elements once indefiniteness is detected, then for a countdown of
+ * iterations (Sec. 2.2, Sec. 5.1).  PPN: Algorithm 1 (Sec. 4). */
+typedef enum { PPN_PN = 0, PPN_PDN = 1, PPN_PPN = 2 } ppn_mode;
+
+/* Arithmetic of the hot path.  Only PPN_FP64 is available in this version;
+ * PPN_MIXED is rejected with PPN_ERR_ARG. */
+typedef enum { PPN_FP64 = 0, PPN_MIXED = 1 } ppn_precision;
+
+/* Newton stopping rule.  VEL (Sec. 5.1): stop once |dx|_inf / h < stop_tol
+ * after the solve, without applying that step.  GRAD_REL: stop at the top of
+ * iteration k once |g^k|_2 <= stop_tol |g^0|_2. */
+typedef enum { PPN_STOP_VEL = 0, PPN_STOP_GRAD_REL = 1 } ppn_stop_mode;
+
+typedef enum {
+  PPN_OK = 0,
+  PPN_ERR_ARG = -1,    /* invalid argument or call order */
+  PPN_ERR_MESH = -2,   /* index out of range, or a rest tet with det(Dm) <= 0 */
+  PPN_ERR_OOM = -3,    /* device allocation failed */
+  PPN_ERR_DEVICE = -4, /* a HIP call failed (message in ppn_last_error) */
+  PPN_ERR_STATE = -5,  /* non-finite positions or velocities */
+  PPN_WARN_NOT_CONVERGED = 1, /* newton_maxit reached; the step was taken */
+  PPN_WARN_LS_FAIL = 2        /* no Armijo step within ls_maxit halvings */
+} ppn_status;
+
+/* Solver parameters.  Defaults (ppn_params_default) follow the paper:
+ * alpha 0.5, beta 2, eps_delta 1e-12 (Sec. 4); eps_clamp 1e-8, PCG relative
+ * tolerance 1e-4, PDN countdown 4, velocity tolerance 1e-3 m/s (Sec. 5.1).
+ * The remaining values are readings: pcg_maxit 10000, newton_maxit 100,
+ * Armijo c 1e-4 with at most 30 halvings, k_dirichlet 1e8 N/m. */
+typedef struct {
+  double alpha;         /* tightening factor, 0 < alpha < 1 */
+  double beta;          /* release factor, >= 1 */
+  double eps_delta;     /* PN fallback threshold on delta */
+  double eps_clamp;     /* eigenvalue clamp eps > 0 */
+  double pcg_rtol;      /* |r|/|r0| */
+  int32_t pcg_maxit;
+  int32_t pdn_countdown;
+  int32_t stop_mode;    /* ppn_stop_mode */
+  int32_t newton_maxit;
+  double stop_tol;
+  double armijo_c;
+  int32_t ls_maxit;
+  int32_t reserved0;
+  double k_dirichlet;   /* penalty stiffness [N/m] */
+} ppn_params;
+
+/* Statistics of one time step. */
+typedef struct {
+  int32_t newton_iters;      /* Newton iterations entered (gradient evaluations) */
+  int32_t pcg_iters;         /* products H d over all solves */
+  int32_t solves;            /* PCG solves actually run */
+  int32_t indefinite_solves; /* solves that reported indefiniteness */
+  int32_t inner_rounds;      /* PPN selection rounds (Algorithm 1 inner loop) */
+  int32_t ls_backtracks;     /* line-search halvings */
+  int32_t safety_events;     /* solves still indefinite with every element projected */
+  int32_t converged;         /* 1 if the stopping rule was met */
+  int32_t ls_fail;           /* 1 if the line search failed */
+  int32_t skipped_solves;    /* PPN rounds that projected nothing new, so the unchanged
+                                system was not solved again (its result is known) */
+  int64_t projected;         /* element Hessians eigendecomposed, summed over iterations */
+  double res0_l2;            /* |g|_2 at the first iterate of the step */
+  double res_l2;             /* |g|_2 at the last evaluated iterate */
+  double res_inf;            /* |g|_inf at the last evaluated iterate */
+  double ms_total;           /* wall time of the step [ms] */
+  double ms_eig;             /* time in the eigen-projection kernel [ms] */
+  double ms_pcg;             /* time in PCG solves [ms] */
+} ppn_step_stats;
+
+/* One record per Newton iteration of the last step (when tracing is on). */
+typedef struct {
+  int32_t k;            /* iteration index within the step */
+  int32_t first_ind;    /* indefiniteness reported by the first solve */
+  int32_t first_iters;  /* PCG iterations of the first solve */
+  int32_t rounds;       /* PPN inner rounds */
+  int32_t n_projected;  /* elements projected in this iteration */
+  int32_t last_ind;     /* indefiniteness of the final solve */
+  double g_l2, g_inf;   /* gradient norms at this iterate */
+  double delta_in;      /* delta on entry (INFINITY if unset) */
+  double delta_out;     /* delta after the relax step */
+  double dx_inf;        /* |dx|_inf of the final direction */
+  double gamma;         /* accepted line-search step (0 if none / converged) */
+} ppn_iter_record;
+
+/* Fill *out with the defaults above. */
+ppn_status ppn_params_default(ppn_params* out);
+
+/* Create an empty scene on the current HIP device.  hip_stream may be NULL
+ * (the library creates a default-priority stream) or a hipStream_t of the
+ * caller, which must outlive the scene. */
+ppn_status ppn_scene_create(ppn_scene** out, void* hip_stream, int32_t precision);
+ppn_status ppn_scene_destroy(ppn_scene* s);
+
+/* Load a tetrahedral mesh: rest positions [n_verts][3], tets [n_tets][4]
+ * (0-based, positively oriented: det[X1-X0, X2-X0, X3-X0] > 0), optional
+ * initial positions (NULL = rest).  Builds the block-sparse pattern and the
+ * element->slot maps, allocates device memory, computes Dm^-1, V_e and the
+ * lumped masses (needs the material; default rho 1000, E 1e5, nu 0.45 until
+ * ppn_set_material is called).  Velocities start at zero.  Errors:
+ * PPN_ERR_MESH for an index out of range or det(Dm) <= 0. */
+ppn_status ppn_load_mesh(ppn_scene* s, int32_t n_verts, const double* rest_xyz,
+                         int32_t n_tets, const int32_t* tets, const double* init_xyz);
+
+/* Density [kg/m^3] and Young's modulus / Poisson ratio, either one value each
+ * (per_element = 0) or one per tet (per_element = 1, arrays of n_tets).
+ * Requires 0 <= nu < 0.5, E >= 0, rho > 0. */
+ppn_status ppn_set_material(ppn_scene* s, double rho, const double* E, const double* nu,
+                            int32_t per_element);
+
+/* Time step h [s] and gravity [3] (m/s^2). */
+ppn_status ppn_set_time_step(ppn_scene* s, double dt, const double* gravity);
+
+/* Dirichlet penalty set: n vertex ids (any order, no duplicates) and their
+ * targets [n][3] at the END of the next time step.  Replaces the previous
+ * set; call again before each step to move the targets. */
+ppn_status ppn_set_dirichlet(ppn_scene* s, int32_t n, const int32_t* vert_ids,
+                             const double* target_xyz);
+
+ppn_status ppn_set_params(ppn_scene* s, const ppn_params* p);
+
+/* Advance one time step with the given Newton variant (Algorithm 1 for
+ * PPN_PPN).  out may be NULL.  Returns PPN_OK, a warning, or an error. */
+ppn_status ppn_newton_step(ppn_scene* s, int32_t mode, ppn_step_stats* out);
+
+/* Current positions: host copy [n_verts][3], or device-to-device copy into a
+ * caller buffer of 3*n_verts doubles ordered on hip_stream (NULL = scene stream). */
+ppn_status ppn_get_positions(ppn_scene* s, double* out_xyz);
+ppn_status ppn_get_positions_dev(ppn_scene* s, void* out_dev, void* hip_stream);
+
+/* Checkpoint / restore of the time-stepping state (positions, velocities).
+ * delta and the PDN countdown are per-step and need no saving. */
+ppn_status ppn_get_state(ppn_scene* s, double* x, double* v);
+ppn_status ppn_set_state(ppn_scene* s, const double* x, const double* v);
+
+ppn_status ppn_get_last_stats(ppn_scene* s, ppn_step_stats* out);
+
+/* Sizes of the loaded scene (any pointer may be NULL). */
+ppn_status ppn_scene_info(ppn_scene* s, int32_t* n_verts, int32_t* n_tets, int32_t* n_edges,
+                          int64_t* n_blocks, int64_t* device_bytes);
+
+/* Message of the last failing call on this handle (or a global message when
+ * s is NULL); valid until the next call on the handle. */
+const char* ppn_last_error(const ppn_scene* s);
+
+/* ---- tracing ------------------------------------------------------------ */
+/* Record one ppn_iter_record per Newton iteration of subsequent steps, plus
+ * the projected element ids of each iteration. */
+ppn_status ppn_set_trace(ppn_scene* s, int32_t enable);
+/* Number of records of the last step. */
+ppn_status ppn_trace_count(ppn_scene* s, int32_t* count);
+/* Record i of the last step; proj_ids (nullable) receives rec->n_projected
+ * ascending element ids. */
+ppn_status ppn_trace_get(ppn_scene* s, int32_t i, ppn_iter_record* rec, int32_t* proj_ids);
+
+/* ---- single stages on caller-given inputs (parity tests, benchmarks) ----- */
+/* The state (x^n, v^n), targets and material of the scene define xhat and the
+ * penalty terms; x is the iterate at which the stage is evaluated. */
+
+/* Unprojected assembled gradient g [3 n_verts] at x (Sec. 3). */
+ppn_status ppn_eval_gradient(ppn_scene* s, const double* x, double* g_out);
+
+/* Element Hessians at x as full 12x12 row-major matrices for the element ids
+ * ids[0..n) (nullable ids = all elements, n = n_tets); the projected ones
+ * (proj_mask[e] != 0, nullable) after eigenvalue clamping (Sec. 3, Eq. (4)). */
+ppn_status ppn_eval_element_hessians(ppn_scene* s, const double* x, const uint8_t* proj_mask,
+                                     int32_t n, const int32_t* ids, double* H_out);
+
+/* Assembled global Hessian at x in 3x3 block-sparse row form, with the
+ * elements in proj_mask (nullable) projected: row_ptr [n_verts+1],
+ * col [n_blocks], vals [n_blocks][9] row-major blocks (Sec. 3, Sec. 4.1). */
+ppn_status ppn_eval_hessian(ppn_scene* s, const double* x, const uint8_t* proj_mask,
+                            int32_t* row_ptr, int32_t* col, double* vals);
+
+/* Selection of Algorithm 1 on a caller-given assembled gradient g [3 n_verts]:
+ * mask_out[e] = 1 iff proj_in[e] == 0 and (|S^e g|_inf > delta or
+ * delta <= eps_delta).  count_out receives the number of ones. */
+ppn_status ppn_select(ppn_scene* s, const double* g, double delta, const uint8_t* proj_in,
+                      uint8_t* mask_out, int32_t* count_out);
+
+/* One block-Jacobi PCG solve H dx = -g at x with proj_mask projected
+ * (Sec. 4.1): returns dx [3 n_verts], the indefiniteness flag and the number
+ * of products H d. */
+ppn_status ppn_solve(ppn_scene* s, const double* x, const uint8_t* proj_mask, double* dx_out,
+                     int32_t* ind_out, int32_t* iters_out);
+
+/* Product q = H d with the Hessian at x (proj_mask projected). */
+ppn_status ppn_hessian_product(ppn_scene* s, const double* x, const uint8_t* proj_mask,
+                               const double* d, double* q_out);
+
+/* Psi(x + gamma_k dx) - Psi(x) for n_gamma step sizes (line search). */
+ppn_status ppn_energy_difference(ppn_scene* s, const double* x, const double* dx, int32_t n_gamma,
+                                 const double* gammas, double* out);
+
+/* Stateless batched projection (Sec. 3, Eq. (4)) of n symmetric 12x12 row-major
+ * matrices in device memory: Hhat = H + sum_{lambda_i < eps} (eps - lambda_i) q_i q_i^T.
+ * In and out may alias.  Runs on hip_stream (NULL = default stream) and
+ * returns after the kernel finished. */
+ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t n, double eps,
+                                 void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPN_H */

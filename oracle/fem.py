@@ -101,6 +101,18 @@ def element_psi(mesh: Mesh, x):
     return out
 
 
+def element_grad(mesh: Mesh, x):
+    """g^e (T,12) for all elements (the gradient half of ``element_grad_hess``)."""
+    g = np.empty((mesh.n_tets, 12))
+    for s in range(0, mesh.n_tets, CHUNK):
+        sel = slice(s, min(mesh.n_tets, s + CHUNK))
+        F = mesh.deformation_gradient(x, sel)
+        B = mesh.B_matrix(sel)
+        P = first_piola(F, mesh.mu[sel], mesh.lam[sel])
+        g[sel] = mesh.V[sel][:, None] * np.einsum("tki,tk->ti", B, vec(P))
+    return g
+
+
 def element_grad_hess(mesh: Mesh, x, idx=None):
     """(g^e (n,12), H^e (n,12,12)), unprojected, for the elements ``idx`` (all if None)."""
     idx = np.arange(mesh.n_tets) if idx is None else np.asarray(idx, dtype=np.int64)

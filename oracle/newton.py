@@ -47,7 +47,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .assemble import Assembler, diagonal_blocks
-from .fem import Mesh, element_grad_hess, element_psi, lumped_mass, predictor
+from .fem import Mesh, element_grad, element_grad_hess, element_psi, lumped_mass, predictor
 from .pcg import pcg_block_jacobi
 from .project import project_to_pd
 
@@ -128,6 +128,31 @@ class Stepper:
         g = self.asm.gradient(ge, self._vertex_gradient_terms(x))
         H = self.asm.hessian(He, self._diag())
         return g, ge, He, H
+
+    def gradient(self, x):
+        """Assembled g (3N,) at x without forming any Hessian."""
+        return self.asm.gradient(element_grad(self.mesh, x), self._vertex_gradient_terms(x))
+
+    def hessian_rows_product(self, x, d, rows, projected=None):
+        """(H d) restricted to the vertex rows ``rows`` (k,3), from the elements
+        incident to those rows only; elements in ``projected`` use Hhat^e."""
+        rows = np.asarray(rows, dtype=np.int64)
+        tets = self.mesh.tets
+        inc = np.nonzero(np.isin(tets, rows).any(axis=1))[0]
+        _, He = element_grad_hess(self.mesh, x, inc)
+        if projected is not None:
+            pm = np.zeros(self.mesh.n_tets, dtype=bool)
+            pm[np.asarray(projected, dtype=np.int64)] = True
+            sel = pm[inc]
+            if sel.any():
+                He[sel] = project_to_pd(He[sel], self.p.eps_clamp)
+        d = np.asarray(d, dtype=np.float64).reshape(-1, 3)
+        ye = np.einsum("tpq,tq->tp", He, d[tets[inc]].reshape(-1, 12)).reshape(-1, 4, 3)
+        out = np.zeros((self.mesh.n_verts, 3))
+        for a in range(4):
+            np.add.at(out, tets[inc, a], ye[:, a])
+        out += self._diag().reshape(-1, 3) * d
+        return out[rows]
 
     def selection_residual(self, g):
         """|S^e g|_inf per element (Sec. 4, projection heuristic)."""

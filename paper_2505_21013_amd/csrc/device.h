@@ -1,0 +1,124 @@
+// Device-side data of one scene and the launchers of the hot-path kernels.
+//
+// Layout in HBM (all FP64 unless noted):
+//   element data   SoA [k][T]: tets (int32, 4), Dm^-1 rows (9), V, mu, lam
+//   vertex vectors AoS [N][3]: x, x^n, v, xhat, g, dx, r, z, d (2 buffers), q
+//   vertex slots   AoS [4T][9]: corner gradient (3) + diagonal block (6)
+//   edge slots     AoS [6T][9]: off-diagonal block, row-major, global orientation
+//   BCSR values    SoA [9][NB] (entry-major, so a 16-lane row group reads
+//                  consecutive doubles per entry), col (int32) [NB], row_ptr [N+1]
+//   block-Jacobi   SoA [9][N]: inverse of each diagonal block
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ppn {
+
+constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels
+
+// Partial-sum slots (each G doubles long) in Dev::part.
+enum PartSlot : int {
+  kPartKappa = 0,  // d^T H d
+  kPartRR = 1,     // r^T r
+  kPartRZ0 = 2,    // r^T z, even iterations
+  kPartRZ1 = 3,    // r^T z, odd iterations
+  kPartSpd = 4,    // count of diagonal blocks failing Sylvester's criterion
+  kPartG2 = 5,     // |g|^2
+  kPartGmax = 6,   // max |g_i|
+  kPartA = 7,      // generic scratch sums (line search uses 7..7+4)
+  kPartCount = 12
+};
+
+struct PcgState {
+  int32_t done;
+  int32_t ind;
+  int32_t iters;
+  int32_t pad;
+  double rr0;
+};
+
+struct Dev {
+  int32_t N = 0, T = 0, E = 0;
+  int64_t NB = 0;
+  int32_t G = 0;          // workgroups of grid-stride reduction kernels (fixed per scene)
+  int32_t rows_per_wg = 0;  // vertex chunk per workgroup (multiple of 16)
+  int32_t nD = 0;         // Dirichlet vertices
+  double h = 1.0 / 30.0;
+  double k_dir = 1e8;
+  double grav[3] = {0, 0, -9.81};
+
+  // mesh
+  int32_t* tets = nullptr;  // [4][T]
+  double* Bm = nullptr;     // [9][T]
+  double* vol = nullptr;    // [T]
+  double* mu = nullptr;     // [T]
+  double* lam = nullptr;    // [T]
+  double* Eyoung = nullptr; // [T]
+  double* nu = nullptr;     // [T]
+  double* mass = nullptr;   // [N]
+  double* X = nullptr;      // [N][3]
+  // maps
+  int32_t* vslot = nullptr;      // [4][T]
+  int32_t* eslot = nullptr;      // [6][T]
+  int32_t* elem_edge = nullptr;  // [6][T]
+  int32_t* vptr = nullptr;       // [N+1]
+  int32_t* vslot_elem = nullptr; // [4T]
+  int32_t* eptr = nullptr;       // [E+1]
+  int32_t* row_ptr = nullptr;    // [N+1]
+  int32_t* col = nullptr;        // [NB]
+  int32_t* diag_blk = nullptr;   // [N]
+  int32_t* eblk_up = nullptr;    // [E]
+  int32_t* eblk_lo = nullptr;    // [E]
+  // slots and matrix
+  double* vslots = nullptr;  // [4T][9]
+  double* eslots = nullptr;  // [6T][9]
+  double* vals = nullptr;    // [9][NB]
+  double* pinv = nullptr;    // [9][N]
+  uint8_t* spd_ok = nullptr; // [N]
+  // Dirichlet
+  int32_t* dir_idx = nullptr;  // [N], -1 if free
+  double* xbar = nullptr;      // [nD][3]
+  // vectors [N][3]
+  double *x = nullptr, *xn = nullptr, *v = nullptr, *xhat = nullptr, *g = nullptr, *dx = nullptr;
+  double *r = nullptr, *z = nullptr, *d0 = nullptr, *d1 = nullptr, *q = nullptr, *xt = nullptr;
+  double* rinf = nullptr;  // [N]
+  // selection
+  uint8_t* proj = nullptr;  // [T]
+  uint8_t* sel = nullptr;   // [T]
+  int32_t* list = nullptr;  // [T]
+  int32_t* sel_cnt = nullptr;  // [n_sel_wg + 1]
+  int32_t n_sel_wg = 0;
+  // reductions and control
+  double* part = nullptr;   // [kPartCount][G]
+  double* scal = nullptr;   // [16] final reduced values
+  PcgState* pcg = nullptr;
+  int32_t* flag = nullptr;  // [4] misc device flags (bad element count, ...)
+};
+
+// ---- launchers (all asynchronous on `st`) --------------------------------
+void launch_precompute(const Dev& D, double rho, hipStream_t st);
+void launch_predict(const Dev& D, hipStream_t st);
+void launch_elem_eval(const Dev& D, hipStream_t st);
+void launch_assemble_full(const Dev& D, hipStream_t st);  // vertex + edge kernels, norm partials
+void launch_reduce(const Dev& D, int first_slot, int n_sum, int n_max, hipStream_t st);
+void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
+void launch_select_count(const Dev& D, double delta, int fallback, hipStream_t st);
+void launch_select_write(const Dev& D, hipStream_t st);
+void launch_eig_all(const Dev& D, double eps, hipStream_t st);
+void launch_eig_list(const Dev& D, int32_t n, double eps, hipStream_t st);
+void launch_regather_list(const Dev& D, int32_t n, hipStream_t st);
+void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st);
+void launch_pcg_init(const Dev& D, hipStream_t st);
+void launch_pcg_iter(const Dev& D, int j, double tol2, int maxit, hipStream_t st);
+void launch_dx_stats(const Dev& D, hipStream_t st);  // |dx|_inf, g.dx -> scal[0..1]
+void launch_safety_dir(const Dev& D, hipStream_t st);
+void launch_rinf_from(const Dev& D, const double* g, hipStream_t st);  // rinf_i = max_c |g_(i,c)|
+void launch_energy_diff(const Dev& D, int n_gamma, const double* gam, hipStream_t st);
+void launch_axpy_x(const Dev& D, double gamma, hipStream_t st);
+void launch_finish_step(const Dev& D, hipStream_t st);
+void launch_spmv_plain(const Dev& D, const double* d, double* q, hipStream_t st);
+void launch_element_hessians(const Dev& D, const int32_t* ids, int32_t n, double* out,
+                             hipStream_t st);
+
+}  // namespace ppn

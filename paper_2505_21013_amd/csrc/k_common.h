@@ -1,0 +1,60 @@
+// Device helpers shared by the kernels: deterministic workgroup reductions and
+// the XCD-aware mapping from workgroup index to a contiguous chunk of rows.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace ppn {
+
+#define PPN_HOST_DEVICE __host__ __device__
+
+// Sum over the 64 lanes of a wavefront; the xor butterfly fixes the order.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum over a 256-thread workgroup, returned to every thread.  lds: 4 doubles.
+__device__ inline double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+__device__ inline double block_max(double v, double* lds) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  return fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+}
+
+// Reduce G per-workgroup partials in a fixed order (every workgroup that calls
+// this gets bit-identical results).
+__device__ inline double reduce_partials(const double* p, int G, double* lds) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < G; i += kBlock) s += p[i];
+  return block_sum(s, lds);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Map the hardware
+// index so that XCD x owns the contiguous logical chunks [x*G/8, (x+1)*G/8):
+// neighbouring rows then share an L2.  Requires G % 8 == 0.
+__device__ inline int logical_wg(int G) {
+  const int b = blockIdx.x;
+  return (b & 7) * (G >> 3) + (b >> 3);
+}
+
+}  // namespace ppn

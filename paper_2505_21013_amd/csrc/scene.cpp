@@ -1,0 +1,709 @@
+// Host orchestration of one time step: PN, PDN and PPN (Algorithm 1) over the
+// device kernels.  The host only reads back the scalars that decide the
+// control flow (gradient norms, solve status, selection count, line-search
+// energies); every vector and matrix operation runs in the kernels.
+#include "scene.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <limits>
+
+namespace ppn {
+
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess)                                                                      \
+      throw HipError{std::string(#x) + ": " + hipGetErrorString(e_),                           \
+                     e_ == hipErrorOutOfMemory ? PPN_ERR_OOM : PPN_ERR_DEVICE};                \
+  } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+static void fail(const std::string& m, ppn_status c = PPN_ERR_ARG) { throw HipError{m, c}; }
+
+void params_defaults(ppn_params* p) {
+  std::memset(p, 0, sizeof(*p));
+  p->alpha = 0.5;
+  p->beta = 2.0;
+  p->eps_delta = 1e-12;
+  p->eps_clamp = 1e-8;
+  p->pcg_rtol = 1e-4;
+  p->pcg_maxit = 10000;
+  p->pdn_countdown = 4;
+  p->stop_mode = PPN_STOP_VEL;
+  p->newton_maxit = 100;
+  p->stop_tol = 1e-3;
+  p->armijo_c = 1e-4;
+  p->ls_maxit = 30;
+  p->k_dirichlet = 1e8;
+}
+
+Scene::Scene(hipStream_t stream, bool own) : st_(stream), own_stream_(own) {
+  params_defaults(&prm_);
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hscal_), 64 * sizeof(double)));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hpcg_), 4 * sizeof(PcgState)));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hint_), 16 * sizeof(int32_t)));
+  HIPCHK(hipEventCreateWithFlags(&ev_[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ev_[1], hipEventDisableTiming));
+  HIPCHK(hipEventCreate(&ev_[2]));
+  HIPCHK(hipEventCreate(&ev_[3]));
+}
+
+Scene::~Scene() {
+  if (st_) (void)hipStreamSynchronize(st_);
+  free_all();
+  if (hscal_) (void)hipHostFree(hscal_);
+  if (hpcg_) (void)hipHostFree(hpcg_);
+  if (hint_) (void)hipHostFree(hint_);
+  for (auto& e : ev_)
+    if (e) (void)hipEventDestroy(e);
+  if (own_stream_ && st_) (void)hipStreamDestroy(st_);
+}
+
+template <class T>
+T* Scene::alloc(size_t n) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) fail("hipMalloc of " + std::to_string(bytes) + " bytes failed", PPN_ERR_OOM);
+  allocs_.push_back(p);
+  dev_bytes_ += int64_t(bytes);
+  return static_cast<T*>(p);
+}
+
+void Scene::free_all() {
+  for (void* p : allocs_) (void)hipFree(p);
+  allocs_.clear();
+  dev_bytes_ = 0;
+  D_ = Dev{};
+}
+
+void Scene::sync() { HIPCHK(hipStreamSynchronize(st_)); }
+
+void Scene::read_scal(int n, double* out) {
+  HIPCHK(hipMemcpyAsync(out, D_.scal, size_t(n) * sizeof(double), hipMemcpyDeviceToHost, st_));
+  sync();
+}
+
+// ---------------------------------------------------------------- set-up
+void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* tets,
+                      const double* init) {
+  if (!rest || !tets) fail("rest_xyz and tets must not be NULL");
+  Topology t;
+  std::string err;
+  if (!build_topology(N, T, tets, t, err)) fail(err, PPN_ERR_MESH);
+  if (loaded()) {
+    sync();
+    free_all();
+  }
+  topo_ = std::move(t);
+  try {
+    Dev D;
+    D.N = N;
+    D.T = T;
+    D.E = topo_.n_edges;
+    D.NB = topo_.n_blocks;
+    int G = (N + 127) / 128;
+    G = std::min(2048, std::max(8, ((G + 7) / 8) * 8));
+    D.G = G;
+    D.rows_per_wg = (((N + G - 1) / G) + 15) / 16 * 16;
+    D.n_sel_wg = (T + kBlock - 1) / kBlock;
+    D.h = D_.h;
+    D.k_dir = prm_.k_dirichlet;
+    std::memcpy(D.grav, D_.grav, sizeof(D.grav));
+    D_ = D;
+    const size_t n = size_t(N), m = size_t(T);
+    D_.tets = alloc<int32_t>(4 * m);
+    D_.Bm = alloc<double>(9 * m);
+    D_.vol = alloc<double>(m);
+    D_.mu = alloc<double>(m);
+    D_.lam = alloc<double>(m);
+    D_.Eyoung = alloc<double>(m);
+    D_.nu = alloc<double>(m);
+    D_.mass = alloc<double>(n);
+    D_.X = alloc<double>(3 * n);
+    D_.vslot = alloc<int32_t>(4 * m);
+    D_.eslot = alloc<int32_t>(6 * m);
+    D_.elem_edge = alloc<int32_t>(6 * m);
+    D_.vptr = alloc<int32_t>(n + 1);
+    D_.vslot_elem = alloc<int32_t>(4 * m);
+    D_.eptr = alloc<int32_t>(size_t(D_.E) + 1);
+    D_.row_ptr = alloc<int32_t>(n + 1);
+    D_.col = alloc<int32_t>(size_t(D_.NB));
+    D_.diag_blk = alloc<int32_t>(n);
+    D_.eblk_up = alloc<int32_t>(size_t(D_.E));
+    D_.eblk_lo = alloc<int32_t>(size_t(D_.E));
+    D_.vslots = alloc<double>(4 * m * 9);
+    D_.eslots = alloc<double>(6 * m * 9);
+    D_.vals = alloc<double>(9 * size_t(D_.NB));
+    D_.pinv = alloc<double>(9 * n);
+    D_.spd_ok = alloc<uint8_t>(n);
+    D_.dir_idx = alloc<int32_t>(n);
+    D_.xbar = alloc<double>(3 * n);
+    double** vecs[] = {&D_.x, &D_.xn, &D_.v, &D_.xhat, &D_.g, &D_.dx,
+                       &D_.r, &D_.z,  &D_.d0, &D_.d1,  &D_.q, &D_.xt};
+    for (double** p : vecs) *p = alloc<double>(3 * n);
+    D_.rinf = alloc<double>(n);
+    D_.proj = alloc<uint8_t>(m);
+    D_.sel = alloc<uint8_t>(m);
+    D_.list = alloc<int32_t>(m);
+    D_.sel_cnt = alloc<int32_t>(size_t(D_.n_sel_wg) + 1);
+    D_.part = alloc<double>(size_t(kPartCount) * G);
+    D_.scal = alloc<double>(16);
+    D_.pcg = alloc<PcgState>(1);
+    D_.flag = alloc<int32_t>(4);
+
+    std::vector<int32_t> soa(4 * m);
+    for (size_t e = 0; e < m; ++e)
+      for (int a = 0; a < 4; ++a) soa[a * m + e] = tets[4 * e + a];
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+      HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_));
+    };
+    up(D_.tets, soa.data(), 4 * m * 4);
+    up(D_.X, rest, 3 * n * 8);
+    up(D_.x, init ? init : rest, 3 * n * 8);
+    HIPCHK(hipMemsetAsync(D_.v, 0, 3 * n * 8, st_));
+    up(D_.vslot, topo_.vslot.data(), 4 * m * 4);
+    up(D_.eslot, topo_.eslot.data(), 6 * m * 4);
+    up(D_.elem_edge, topo_.elem_edge.data(), 6 * m * 4);
+    up(D_.vptr, topo_.vptr.data(), (n + 1) * 4);
+    up(D_.vslot_elem, topo_.vslot_elem.data(), 4 * m * 4);
+    up(D_.eptr, topo_.eptr.data(), (size_t(D_.E) + 1) * 4);
+    up(D_.row_ptr, topo_.row_ptr.data(), (n + 1) * 4);
+    up(D_.col, topo_.col.data(), size_t(D_.NB) * 4);
+    up(D_.diag_blk, topo_.diag_blk.data(), n * 4);
+    up(D_.eblk_up, topo_.eblk_up.data(), size_t(D_.E) * 4);
+    up(D_.eblk_lo, topo_.eblk_lo.data(), size_t(D_.E) * 4);
+    X_.assign(rest, rest + 3 * n);
+    if (E_.size() != m) {
+      const double e0 = E_.empty() ? 1e5 : E_[0], n0 = nu_.empty() ? 0.45 : nu_[0];
+      E_.assign(m, e0);
+      nu_.assign(m, n0);
+    }
+    dir_ids_.clear();
+    dir_tgt_.clear();
+    dirichlet_dirty_ = true;
+    upload_dirichlet();
+    material_dirty_ = true;
+    upload_material();
+    sync();
+  } catch (...) {
+    (void)hipStreamSynchronize(st_);
+    free_all();
+    throw;
+  }
+}
+
+void Scene::upload_material() {
+  if (!loaded() || !material_dirty_) return;
+  const size_t m = size_t(D_.T);
+  HIPCHK(hipMemcpyAsync(D_.Eyoung, E_.data(), m * 8, hipMemcpyHostToDevice, st_));
+  HIPCHK(hipMemcpyAsync(D_.nu, nu_.data(), m * 8, hipMemcpyHostToDevice, st_));
+  HIPCHK(hipMemsetAsync(D_.flag, 0, 4 * sizeof(int32_t), st_));
+  launch_precompute(D_, rho_, st_);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(hint_, D_.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+  sync();
+  if (hint_[0] != 0)
+    fail(std::to_string(hint_[0]) + " rest tetrahedra have det(Dm) <= 0", PPN_ERR_MESH);
+  material_dirty_ = false;
+}
+
+void Scene::set_material(double rho, const double* E, const double* nu, bool per_element) {
+  if (!(rho > 0.0) || !E || !nu) fail("rho must be > 0 and E, nu non-NULL");
+  if (per_element && !loaded()) fail("per-element material needs a loaded mesh");
+  const size_t m = per_element ? size_t(D_.T) : 1;
+  for (size_t k = 0; k < m; ++k)
+    if (!(E[k] >= 0.0) || !(nu[k] >= 0.0 && nu[k] < 0.5)) fail("need E >= 0 and 0 <= nu < 0.5");
+  rho_ = rho;
+  const size_t T = loaded() ? size_t(D_.T) : 1;
+  E_.resize(T);
+  nu_.resize(T);
+  for (size_t e = 0; e < T; ++e) {
+    E_[e] = per_element ? E[e] : E[0];
+    nu_[e] = per_element ? nu[e] : nu[0];
+  }
+  material_dirty_ = true;
+  if (loaded()) upload_material();
+}
+
+void Scene::set_time_step(double dt, const double* gravity) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) fail("dt must be finite and > 0");
+  D_.h = dt;
+  if (gravity)
+    for (int c = 0; c < 3; ++c) D_.grav[c] = gravity[c];
+}
+
+void Scene::upload_dirichlet() {
+  if (!loaded() || !dirichlet_dirty_) return;
+  const int32_t N = D_.N;
+  std::vector<int32_t> idx(N, -1);
+  for (size_t k = 0; k < dir_ids_.size(); ++k) idx[dir_ids_[k]] = int32_t(k);
+  HIPCHK(hipMemcpyAsync(D_.dir_idx, idx.data(), size_t(N) * 4, hipMemcpyHostToDevice, st_));
+  if (!dir_tgt_.empty())
+    HIPCHK(hipMemcpyAsync(D_.xbar, dir_tgt_.data(), dir_tgt_.size() * 8, hipMemcpyHostToDevice, st_));
+  D_.nD = int32_t(dir_ids_.size());
+  sync();
+  dirichlet_dirty_ = false;
+}
+
+void Scene::set_dirichlet(int32_t n, const int32_t* ids, const double* targets) {
+  if (!loaded()) fail("load the mesh before setting Dirichlet constraints");
+  if (n < 0 || (n > 0 && (!ids || !targets))) fail("bad Dirichlet arguments");
+  std::vector<uint8_t> seen(D_.N, 0);
+  for (int32_t k = 0; k < n; ++k) {
+    if (ids[k] < 0 || ids[k] >= D_.N) fail("Dirichlet vertex id out of range");
+    if (seen[ids[k]]++) fail("duplicate Dirichlet vertex id");
+  }
+  for (int64_t k = 0; k < 3 * int64_t(n); ++k)
+    if (!std::isfinite(targets[k])) fail("non-finite Dirichlet target");
+  const bool same_ids = int32_t(dir_ids_.size()) == n && std::equal(ids, ids + n, dir_ids_.begin());
+  dir_tgt_.assign(targets, targets + 3 * size_t(n));
+  if (same_ids && !dirichlet_dirty_) {
+    if (n > 0)
+      HIPCHK(hipMemcpyAsync(D_.xbar, dir_tgt_.data(), dir_tgt_.size() * 8, hipMemcpyHostToDevice, st_));
+    sync();
+    return;
+  }
+  dir_ids_.assign(ids, ids + n);
+  dirichlet_dirty_ = true;
+  upload_dirichlet();
+}
+
+void Scene::set_params(const ppn_params& p) {
+  if (!(p.alpha > 0.0 && p.alpha < 1.0)) fail("alpha must be in (0, 1)");
+  if (!(p.beta >= 1.0)) fail("beta must be >= 1");
+  if (!(p.eps_clamp > 0.0) || !(p.eps_delta >= 0.0)) fail("eps_clamp > 0 and eps_delta >= 0 required");
+  if (!(p.pcg_rtol > 0.0 && p.pcg_rtol < 1.0) || p.pcg_maxit < 1) fail("bad PCG tolerance or cap");
+  if (p.stop_mode != PPN_STOP_VEL && p.stop_mode != PPN_STOP_GRAD_REL) fail("bad stop_mode");
+  if (!(p.stop_tol >= 0.0) || p.newton_maxit < 1 || p.ls_maxit < 0 || p.pdn_countdown < 0)
+    fail("bad Newton / line-search parameters");
+  if (!(p.armijo_c > 0.0 && p.armijo_c < 1.0)) fail("armijo_c must be in (0, 1)");
+  if (!(p.k_dirichlet >= 0.0)) fail("k_dirichlet must be >= 0");
+  prm_ = p;
+  D_.k_dir = p.k_dirichlet;
+}
+
+// ---------------------------------------------------------------- building blocks
+void Scene::evaluate_at_current_x() {
+  launch_fill_u8(D_.proj, 0, D_.T, st_);
+  launch_elem_eval(D_, st_);
+  launch_assemble_full(D_, st_);
+  launch_reduce(D_, kPartG2, 1, 1, st_);
+  LAUNCHCHK();
+  n_projected_ = 0;
+  all_projected_ = false;
+}
+
+void Scene::project_all() {
+  HIPCHK(hipEventRecord(ev_[2], st_));
+  launch_eig_all(D_, prm_.eps_clamp, st_);
+  hipEvent_t stop = ev_[3];
+  HIPCHK(hipEventRecord(stop, st_));
+  launch_fill_u8(D_.proj, 1, D_.T, st_);
+  launch_assemble_full(D_, st_);
+  LAUNCHCHK();
+  HIPCHK(hipEventSynchronize(stop));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ev_[2], stop));
+  last_stats.ms_eig += ms;
+  last_stats.projected += D_.T - n_projected_;
+  n_projected_ = D_.T;
+  all_projected_ = true;
+}
+
+int32_t Scene::select_and_project(double delta, bool fallback) {
+  launch_select_count(D_, delta, fallback ? 1 : 0, st_);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(hint_, D_.sel_cnt + D_.n_sel_wg, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+  sync();
+  const int32_t n = hint_[0];
+  if (n <= 0) return 0;
+  launch_select_write(D_, st_);
+  HIPCHK(hipEventRecord(ev_[2], st_));
+  launch_eig_list(D_, n, prm_.eps_clamp, st_);
+  hipEvent_t stop = ev_[3];
+  HIPCHK(hipEventRecord(stop, st_));
+  if (int64_t(n) * 8 > D_.T)
+    launch_assemble_full(D_, st_);
+  else
+    launch_regather_list(D_, n, st_);
+  LAUNCHCHK();
+  HIPCHK(hipEventSynchronize(stop));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ev_[2], stop));
+  last_stats.ms_eig += ms;
+  last_stats.projected += n;
+  n_projected_ += n;
+  all_projected_ = n_projected_ >= D_.T;
+  return n;
+}
+
+void Scene::project_mask(const uint8_t* mask) {
+  if (!mask) return;
+  std::vector<int32_t> ids;
+  for (int32_t e = 0; e < D_.T; ++e)
+    if (mask[e]) ids.push_back(e);
+  HIPCHK(hipMemcpyAsync(D_.proj, mask, size_t(D_.T), hipMemcpyHostToDevice, st_));
+  if (ids.empty()) return;
+  HIPCHK(hipMemcpyAsync(D_.list, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, st_));
+  launch_eig_list(D_, int32_t(ids.size()), prm_.eps_clamp, st_);
+  launch_regather_list(D_, int32_t(ids.size()), st_);
+  LAUNCHCHK();
+  sync();
+}
+
+void Scene::solve(int32_t& ind, int32_t& iters) {
+  const auto t0 = std::chrono::steady_clock::now();
+  launch_pcg_init(D_, st_);
+  LAUNCHCHK();
+  const double tol2 = prm_.pcg_rtol * prm_.pcg_rtol;
+  const int maxit = prm_.pcg_maxit;
+  int j = 0, chunk = 8, slot = 0;
+  bool pending = false;
+  while (j <= maxit) {
+    const int jend = std::min(j + chunk, maxit + 1);
+    for (; j < jend; ++j) launch_pcg_iter(D_, j, tol2, maxit, st_);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(&hpcg_[slot], D_.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipEventRecord(ev_[slot], st_));
+    if (pending) {
+      HIPCHK(hipEventSynchronize(ev_[slot ^ 1]));
+      if (hpcg_[slot ^ 1].done) break;
+    }
+    pending = true;
+    slot ^= 1;
+    chunk = std::min(chunk * 2, 64);
+  }
+  HIPCHK(hipMemcpyAsync(&hpcg_[2], D_.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, st_));
+  sync();
+  if (!hpcg_[2].done) fail("PCG ended without a decision", PPN_ERR_DEVICE);
+  ind = hpcg_[2].ind;
+  iters = hpcg_[2].iters;
+  last_stats.ms_pcg +=
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------- one time step
+ppn_status Scene::newton_step(int mode, ppn_step_stats* out) {
+  if (!loaded()) fail("no mesh loaded");
+  if (mode != PPN_PN && mode != PPN_PDN && mode != PPN_PPN) fail("unknown mode");
+  upload_material();
+  upload_dirichlet();
+  const auto t0 = std::chrono::steady_clock::now();
+  last_stats = ppn_step_stats{};
+  ppn_step_stats& S = last_stats;
+  trace.clear();
+  trace_ids.clear();
+  const double h = D_.h;
+  launch_predict(D_, st_);
+  LAUNCHCHK();
+  double delta = std::numeric_limits<double>::infinity();
+  int countdown = 0;
+  double g0 = 0.0;
+  bool converged = false;
+  ppn_status status = PPN_OK;
+
+  for (int k = 0; k < prm_.newton_maxit; ++k) {
+    S.newton_iters++;
+    ppn_iter_record rec{};
+    rec.k = k;
+    rec.delta_in = delta;
+    evaluate_at_current_x();
+    read_scal(2, hscal_);
+    const double g_l2 = std::sqrt(hscal_[0]), g_inf = hscal_[1];
+    if (!std::isfinite(g_l2)) fail("non-finite gradient", PPN_ERR_STATE);
+    S.res_l2 = g_l2;
+    S.res_inf = g_inf;
+    rec.g_l2 = g_l2;
+    rec.g_inf = g_inf;
+    if (k == 0) {
+      g0 = g_l2;
+      S.res0_l2 = g_l2;
+    }
+    if (prm_.stop_mode == PPN_STOP_GRAD_REL && g_l2 <= prm_.stop_tol * g0) {
+      converged = true;
+      rec.delta_out = delta;
+      if (trace_on) {
+        trace.push_back(rec);
+        trace_ids.emplace_back();
+      }
+      break;
+    }
+    if (mode == PPN_PN || (mode == PPN_PDN && countdown > 0)) {
+      project_all();
+      if (mode == PPN_PDN) countdown--;
+    }
+    int32_t ind = 0, it = 0;
+    solve(ind, it);
+    S.solves++;
+    S.pcg_iters += it;
+    S.indefinite_solves += ind;
+    rec.first_ind = ind;
+    rec.first_iters = it;
+    if (mode == PPN_PDN && ind && !all_projected_) {
+      project_all();
+      solve(ind, it);
+      S.solves++;
+      S.pcg_iters += it;
+      S.indefinite_solves += ind;
+      countdown = prm_.pdn_countdown;
+    }
+    if (mode == PPN_PPN) {
+      while (ind) {
+        if (std::isinf(delta)) delta = prm_.alpha * g_inf;
+        const int32_t n_new = select_and_project(delta, delta <= prm_.eps_delta);
+        S.inner_rounds++;
+        rec.rounds++;
+        if (n_new > 0) {
+          solve(ind, it);
+          S.solves++;
+          S.pcg_iters += it;
+          S.indefinite_solves += ind;
+        } else {
+          // Nothing new was projected: H is unchanged and the solve would
+          // repeat the previous one exactly (still indefinite).
+          S.skipped_solves++;
+        }
+        if (ind) delta = prm_.alpha * delta;
+        if (ind && all_projected_) break;
+      }
+      delta = prm_.beta * delta;
+    }
+    rec.last_ind = ind;
+    rec.delta_out = delta;
+    rec.n_projected = n_projected_;
+    if (ind) {
+      S.safety_events++;
+      launch_dx_stats(D_, st_);
+      read_scal(2, hscal_);
+      if (hscal_[1] == 0.0) launch_safety_dir(D_, st_);
+    }
+    launch_dx_stats(D_, st_);
+    LAUNCHCHK();
+    read_scal(2, hscal_);
+    const double gdx = hscal_[0], dx_inf = hscal_[1];
+    rec.dx_inf = dx_inf;
+    if (trace_on) {
+      std::vector<uint8_t> pm(size_t(D_.T));
+      HIPCHK(hipMemcpyAsync(pm.data(), D_.proj, pm.size(), hipMemcpyDeviceToHost, st_));
+      sync();
+      std::vector<int32_t> ids;
+      for (int32_t e = 0; e < D_.T; ++e)
+        if (pm[e]) ids.push_back(e);
+      trace_ids.push_back(std::move(ids));
+    }
+    if (prm_.stop_mode == PPN_STOP_VEL && dx_inf / h < prm_.stop_tol) {
+      converged = true;
+      if (trace_on) trace.push_back(rec);
+      break;
+    }
+    // Armijo backtracking, four trial steps per kernel launch.
+    bool accepted = false;
+    double gamma = 0.0;
+    int trial = 0;
+    while (trial <= prm_.ls_maxit && !accepted) {
+      const int nb = std::min(4, prm_.ls_maxit + 1 - trial);
+      double gam[4];
+      for (int q = 0; q < nb; ++q) gam[q] = std::ldexp(1.0, -(trial + q));
+      launch_energy_diff(D_, nb, gam, st_);
+      LAUNCHCHK();
+      read_scal(nb, hscal_);
+      int q = 0;
+      for (; q < nb; ++q)
+        if (hscal_[q] <= prm_.armijo_c * gam[q] * gdx) {
+          accepted = true;
+          gamma = gam[q];
+          break;
+        }
+      trial += q;
+    }
+    S.ls_backtracks += trial;
+    rec.gamma = accepted ? gamma : 0.0;
+    if (trace_on) trace.push_back(rec);
+    if (!accepted) {
+      S.ls_fail = 1;
+      status = PPN_WARN_LS_FAIL;
+      break;
+    }
+    launch_axpy_x(D_, gamma, st_);
+    LAUNCHCHK();
+  }
+  if (!converged && status == PPN_OK) status = PPN_WARN_NOT_CONVERGED;
+  launch_finish_step(D_, st_);
+  LAUNCHCHK();
+  sync();
+  S.converged = converged ? 1 : 0;
+  S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (out) *out = S;
+  return status;
+}
+
+// ---------------------------------------------------------------- stage entry points
+// xhat comes from the scene state (x^n, v^n); the caller's x replaces the
+// iterate for the duration of the call and the state is restored afterwards.
+void Scene::stage_state(const double* x) {
+  if (!loaded()) fail("no mesh loaded");
+  if (!x) fail("x must not be NULL");
+  upload_material();
+  upload_dirichlet();
+  launch_predict(D_, st_);
+  HIPCHK(hipMemcpyAsync(D_.x, x, size_t(D_.N) * 24, hipMemcpyHostToDevice, st_));
+}
+
+struct RestoreX {
+  Scene* s;
+  const Dev& D;
+  hipStream_t st;
+  ~RestoreX() {
+    (void)hipMemcpyAsync(D.x, D.xn, size_t(D.N) * 24, hipMemcpyDeviceToDevice, st);
+    (void)hipStreamSynchronize(st);
+  }
+};
+
+void Scene::eval_gradient(const double* x, double* g) {
+  stage_state(x);
+  RestoreX r{this, D_, st_};
+  evaluate_at_current_x();
+  HIPCHK(hipMemcpyAsync(g, D_.g, size_t(D_.N) * 24, hipMemcpyDeviceToHost, st_));
+  sync();
+}
+
+void Scene::eval_element_hessians(const double* x, const uint8_t* mask, int32_t n,
+                                  const int32_t* ids, double* out) {
+  if (!out) fail("H_out must not be NULL");
+  stage_state(x);
+  RestoreX r{this, D_, st_};
+  evaluate_at_current_x();
+  project_mask(mask);
+  if (!ids) n = D_.T;
+  int32_t* dids = nullptr;
+  if (ids) {
+    for (int32_t k = 0; k < n; ++k)
+      if (ids[k] < 0 || ids[k] >= D_.T) fail("element id out of range");
+    HIPCHK(hipMalloc(&dids, std::max<size_t>(1, size_t(n)) * 4));
+    HIPCHK(hipMemcpyAsync(dids, ids, size_t(n) * 4, hipMemcpyHostToDevice, st_));
+  }
+  double* dout = nullptr;
+  HIPCHK(hipMalloc(&dout, std::max<size_t>(1, size_t(n)) * 144 * 8));
+  launch_element_hessians(D_, dids, n, dout, st_);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, size_t(n) * 144 * 8, hipMemcpyDeviceToHost, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  (void)hipFree(dout);
+  if (dids) (void)hipFree(dids);
+  HIPCHK(e);
+}
+
+void Scene::eval_hessian(const double* x, const uint8_t* mask, int32_t* row_ptr, int32_t* col,
+                         double* vals) {
+  stage_state(x);
+  RestoreX r{this, D_, st_};
+  evaluate_at_current_x();
+  project_mask(mask);
+  if (vals) {
+    const size_t NB = size_t(D_.NB);
+    std::vector<double> soa(9 * NB);
+    HIPCHK(hipMemcpyAsync(soa.data(), D_.vals, soa.size() * 8, hipMemcpyDeviceToHost, st_));
+    sync();
+    for (size_t b = 0; b < NB; ++b)
+      for (int c = 0; c < 9; ++c) vals[9 * b + c] = soa[c * NB + b];
+  }
+  if (row_ptr) std::copy(topo_.row_ptr.begin(), topo_.row_ptr.end(), row_ptr);
+  if (col) std::copy(topo_.col.begin(), topo_.col.end(), col);
+}
+
+void Scene::select(const double* g, double delta, const uint8_t* proj_in, uint8_t* mask,
+                   int32_t* cnt) {
+  if (!loaded()) fail("no mesh loaded");
+  if (!g) fail("g must not be NULL");
+  HIPCHK(hipMemcpyAsync(D_.xt, g, size_t(D_.N) * 24, hipMemcpyHostToDevice, st_));
+  launch_rinf_from(D_, D_.xt, st_);
+  if (proj_in)
+    HIPCHK(hipMemcpyAsync(D_.proj, proj_in, size_t(D_.T), hipMemcpyHostToDevice, st_));
+  else
+    launch_fill_u8(D_.proj, 0, D_.T, st_);
+  launch_select_count(D_, delta, delta <= prm_.eps_delta ? 1 : 0, st_);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(hint_, D_.sel_cnt + D_.n_sel_wg, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+  if (mask) HIPCHK(hipMemcpyAsync(mask, D_.sel, size_t(D_.T), hipMemcpyDeviceToHost, st_));
+  sync();
+  if (cnt) *cnt = hint_[0];
+}
+
+void Scene::solve_at(const double* x, const uint8_t* mask, double* dx, int32_t* ind,
+                     int32_t* iters) {
+  stage_state(x);
+  RestoreX r{this, D_, st_};
+  evaluate_at_current_x();
+  project_mask(mask);
+  int32_t i1 = 0, i2 = 0;
+  solve(i1, i2);
+  if (dx) HIPCHK(hipMemcpyAsync(dx, D_.dx, size_t(D_.N) * 24, hipMemcpyDeviceToHost, st_));
+  sync();
+  if (ind) *ind = i1;
+  if (iters) *iters = i2;
+}
+
+void Scene::hessian_product(const double* x, const uint8_t* mask, const double* d, double* q) {
+  if (!d || !q) fail("d and q must not be NULL");
+  stage_state(x);
+  RestoreX r{this, D_, st_};
+  evaluate_at_current_x();
+  project_mask(mask);
+  HIPCHK(hipMemcpyAsync(D_.xt, d, size_t(D_.N) * 24, hipMemcpyHostToDevice, st_));
+  launch_spmv_plain(D_, D_.xt, D_.q, st_);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(q, D_.q, size_t(D_.N) * 24, hipMemcpyDeviceToHost, st_));
+  sync();
+}
+
+void Scene::energy_difference(const double* x, const double* dx, int32_t n, const double* gam,
+                              double* out) {
+  if (!dx || !gam || !out || n < 0) fail("bad energy_difference arguments");
+  stage_state(x);
+  RestoreX r{this, D_, st_};
+  HIPCHK(hipMemcpyAsync(D_.dx, dx, size_t(D_.N) * 24, hipMemcpyHostToDevice, st_));
+  for (int32_t k = 0; k < n; k += 4) {
+    const int nb = std::min(4, n - k);
+    launch_energy_diff(D_, nb, gam + k, st_);
+    LAUNCHCHK();
+    read_scal(nb, hscal_);
+    for (int q = 0; q < nb; ++q) out[k + q] = hscal_[q];
+  }
+}
+
+void Scene::get_positions(double* out) {
+  if (!loaded()) fail("no mesh loaded");
+  HIPCHK(hipMemcpyAsync(out, D_.x, size_t(D_.N) * 24, hipMemcpyDeviceToHost, st_));
+  sync();
+}
+
+void Scene::get_positions_dev(void* out, hipStream_t st) {
+  if (!loaded()) fail("no mesh loaded");
+  sync();
+  HIPCHK(hipMemcpyAsync(out, D_.x, size_t(D_.N) * 24, hipMemcpyDeviceToDevice, st ? st : st_));
+  if (!st) sync();
+}
+
+void Scene::get_state(double* x, double* v) {
+  if (!loaded()) fail("no mesh loaded");
+  if (x) HIPCHK(hipMemcpyAsync(x, D_.x, size_t(D_.N) * 24, hipMemcpyDeviceToHost, st_));
+  if (v) HIPCHK(hipMemcpyAsync(v, D_.v, size_t(D_.N) * 24, hipMemcpyDeviceToHost, st_));
+  sync();
+}
+
+void Scene::set_state(const double* x, const double* v) {
+  if (!loaded()) fail("no mesh loaded");
+  const size_t n = size_t(D_.N) * 3;
+  for (size_t k = 0; k < n; ++k)
+    if ((x && !std::isfinite(x[k])) || (v && !std::isfinite(v[k])))
+      fail("non-finite state", PPN_ERR_STATE);
+  if (x) HIPCHK(hipMemcpyAsync(D_.x, x, n * 8, hipMemcpyHostToDevice, st_));
+  if (v) HIPCHK(hipMemcpyAsync(D_.v, v, n * 8, hipMemcpyHostToDevice, st_));
+  sync();
+}
+
+}  // namespace ppn

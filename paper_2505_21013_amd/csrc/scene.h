@@ -1,0 +1,99 @@
+// Scene: owns the device buffers of one simulation and runs its time steps.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/ppn.h"
+#include "device.h"
+#include "topology.h"
+
+namespace ppn {
+
+struct HipError {
+  std::string msg;
+  ppn_status code;
+};
+
+class Scene {
+ public:
+  Scene(hipStream_t stream, bool own_stream);
+  ~Scene();
+
+  void load_mesh(int32_t n_verts, const double* rest, int32_t n_tets, const int32_t* tets,
+                 const double* init);
+  void set_material(double rho, const double* E, const double* nu, bool per_element);
+  void set_time_step(double dt, const double* gravity);
+  void set_dirichlet(int32_t n, const int32_t* ids, const double* targets);
+  void set_params(const ppn_params& p);
+  ppn_status newton_step(int mode, ppn_step_stats* out);
+
+  // stage entry points
+  void eval_gradient(const double* x, double* g);
+  void eval_element_hessians(const double* x, const uint8_t* mask, int32_t n, const int32_t* ids,
+                             double* out);
+  void eval_hessian(const double* x, const uint8_t* mask, int32_t* row_ptr, int32_t* col,
+                    double* vals);
+  void select(const double* g, double delta, const uint8_t* proj_in, uint8_t* mask, int32_t* cnt);
+  void solve_at(const double* x, const uint8_t* mask, double* dx, int32_t* ind, int32_t* iters);
+  void hessian_product(const double* x, const uint8_t* mask, const double* d, double* q);
+  void energy_difference(const double* x, const double* dx, int32_t n, const double* gam,
+                         double* out);
+
+  void get_positions(double* out);
+  void get_positions_dev(void* out, hipStream_t st);
+  void get_state(double* x, double* v);
+  void set_state(const double* x, const double* v);
+
+  bool loaded() const { return D_.N > 0; }
+  const Dev& dev() const { return D_; }
+  const Topology& topo() const { return topo_; }
+  int64_t device_bytes() const { return dev_bytes_; }
+
+  ppn_step_stats last_stats{};
+  std::string last_error;
+  bool trace_on = false;
+  std::vector<ppn_iter_record> trace;
+  std::vector<std::vector<int32_t>> trace_ids;
+
+ private:
+  template <class T>
+  T* alloc(size_t n);
+  void free_all();
+  void upload_material();
+  void upload_dirichlet();
+  void sync();
+  void stage_state(const double* x);
+  void evaluate_at_current_x();
+  void project_mask(const uint8_t* mask);
+  void project_all();
+  int32_t select_and_project(double delta, bool fallback);
+  void solve(int32_t& ind, int32_t& iters);
+  void read_scal(int n, double* out);
+
+  hipStream_t st_;
+  bool own_stream_;
+  Dev D_;
+  Topology topo_;
+  std::vector<void*> allocs_;
+  int64_t dev_bytes_ = 0;
+  ppn_params prm_{};
+  // host copies
+  std::vector<double> X_, E_, nu_;
+  double rho_ = 1000.0;
+  std::vector<int32_t> dir_ids_;
+  std::vector<double> dir_tgt_;
+  bool material_dirty_ = true;
+  bool dirichlet_dirty_ = true;
+  // pinned host scratch
+  double* hscal_ = nullptr;
+  PcgState* hpcg_ = nullptr;
+  int32_t* hint_ = nullptr;
+  hipEvent_t ev_[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool all_projected_ = false;
+  int32_t n_projected_ = 0;
+};
+
+}  // namespace ppn

@@ -1,0 +1,54 @@
+// Host-side sparsity and scatter-map construction for the tetrahedral mesh.
+//
+// The global Hessian H = sum_e H^e (Sec. 3) has one 3x3 block per vertex
+// pair that shares an element; its sparsity never changes (Sec. 4.1).  The
+// element kernel writes each element's blocks into "slots" ordered by the
+// block they belong to, so that assembly is a contiguous segmented sum per
+// block with no atomics and a fixed summation order:
+//
+//  * vertex slots: one per (element, corner), grouped by vertex and, within a
+//    vertex, ascending by element.  A slot holds the corner's gradient (3) and
+//    its diagonal Hessian block (6, symmetric upper).
+//  * edge slots: one per (element, vertex pair), grouped by the edge (lo, hi)
+//    with lo < hi, ascending by element.  A slot holds the 3x3 off-diagonal
+//    block H_(lo,hi) in global orientation (row = lo vertex).
+//
+// The block-sparse matrix is stored full (both triangles) with columns
+// ascending in each row and the diagonal block included.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ppn {
+
+// Local vertex pairs of a tetrahedron, in the order used for edge slots.
+constexpr int kPairA[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kPairC[6] = {1, 2, 3, 2, 3, 3};
+
+struct Topology {
+  int32_t n_verts = 0, n_tets = 0, n_edges = 0;
+  int64_t n_blocks = 0;
+  // element -> slot maps, SoA: [corner or pair][element]
+  std::vector<int32_t> vslot;      // [4][T]
+  std::vector<int32_t> eslot;      // [6][T]
+  std::vector<int32_t> elem_edge;  // [6][T] edge id of each pair
+  // slot ranges
+  std::vector<int32_t> vptr;       // [N+1]
+  std::vector<int32_t> vslot_elem; // [4T] element owning each vertex slot
+  std::vector<int32_t> eptr;       // [E+1]
+  std::vector<int32_t> edge_lo, edge_hi;  // [E]
+  // block-sparse rows
+  std::vector<int32_t> row_ptr;    // [N+1]
+  std::vector<int32_t> col;        // [NB]
+  std::vector<int32_t> diag_blk;   // [N]
+  std::vector<int32_t> eblk_up;    // [E] block (lo, hi)
+  std::vector<int32_t> eblk_lo;    // [E] block (hi, lo)
+};
+
+// Builds the topology from tets [T][4] (AoS, 0-based).  Returns false and sets
+// err when an index is out of range or an element repeats a vertex.
+bool build_topology(int32_t n_verts, int32_t n_tets, const int32_t* tets, Topology& out,
+                    std::string& err);
+
+}  // namespace ppn
