@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark: PPN backward-Euler time steps per second on one MI355X.
+
+Workload (default): cube of 64^3 hex cells split into 1,572,864 linear tets
+(274,625 vertices), Stable Neo-Hookean with E log-uniform in [1e4, 1e6] Pa per
+element, nu = 0.48, rho = 1000, dt = 1/30 s, gravity, bottom face pinned and top
+face pushed down 60% over 50 steps; PPN (Algorithm 1) in FP64; stop when the
+Newton velocity step is below 1e-3 m/s.  Inputs are seeded and synthetic.
+
+A "step" is one time step (a full Newton minimisation through every stage of
+the hot path).  W warm-up steps run first on the same scene, the state is then
+reset to the initial one, and K steps (1..K of the schedule) are timed between
+two device synchronisations.  All data are resident in HBM before timing.
+
+Printed as one JSON line: steps/s (value), per-step latency p50/p99, in-situ
+eigen-projections/s, the roofline of the dominant kernel (the PCG matrix
+product, timed live with HIP events on the scene stream) and the oracle's CPU
+baseline on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def spmv_bytes(N, NB):
+    """Algorithmic bytes of one PCG matrix-product launch: every block value
+    (72 B) and column index (4 B), the row pointers, the gathered z and
+    previous direction (24 B each per vertex), and the new direction and
+    product written (24 B each per vertex)."""
+    return 76 * NB + 4 * (N + 1) + 4 * 24 * N
+
+
+def cpu_baseline(cfg, per_step_counts):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "oracle.baseline", "--config", str(cfg)], cwd=ROOT,
+                       capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    c = json.loads(r.stdout.strip().splitlines()[-1])
+    from oracle.baseline import per_step_seconds
+    sec = per_step_seconds(c, per_step_counts)
+    return {"value": 1.0 / sec, "unit": "steps/s", "cores": c["threads"], "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle, 1 thread, on the same workload: element evaluation + "
+                       f"assembly of {c['n_sample']} elements, clamping of {c['n_proj']} element "
+                       f"Hessians, {c['pcg_iters_timed']} PCG iterations on the partial operator and one "
+                       f"line-search energy pass, timed ({c['wall_s']:.1f} s) and scaled per element / per "
+                       f"nonzero to the full mesh with the timed run's mean per-step counts"),
+            "s_per_step": sec}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, help="workload index (2 = 1.57M-tet cube)")
+    ap.add_argument("--mode", default="PPN", choices=["PN", "PDN", "PPN"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stats-out", default=None, help="write per-step stats JSON here")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run 5 plain device copies of this many MiB (HBM counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
+              "note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if a.calibrate_copy_mib:
+        n = a.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
+        return
+
+    from paper_2505_21013_amd import scene_from
+    from scenes import config
+
+    torch.cuda.set_device(0)
+    sc = config(a.config)
+    stream = torch.cuda.current_stream().cuda_stream
+    s = scene_from(sc, stream=stream)
+    info = s.ppn_scene_info()
+
+    for n in range(1, a.warmup + 1):
+        s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
+        st = s.ppn_newton_step(a.mode)
+        print(f"warmup {n}: {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    s.ppn_set_state(sc.x0, sc.v0)
+    s.ppn_set_profiling(True)
+
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(1, a.steps + 1):
+        ts = time.perf_counter()
+        s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
+        st = s.ppn_newton_step(a.mode)
+        st["wall_ms"] = (time.perf_counter() - ts) * 1e3
+        stats.append(st)
+        print(f"step {n}: {st['wall_ms']:.1f} ms newton {st['newton_iters']} pcg {st['pcg_iters']} "
+              f"projected {st['projected']} {st['status']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    K = a.steps
+    lat = np.array([st["wall_ms"] for st in stats])
+    tot = {k: sum(st[k] for st in stats) for k in
+           ("newton_iters", "pcg_iters", "solves", "projected", "ms_eig", "ms_spmv", "n_spmv",
+            "ls_backtracks", "inner_rounds")}
+    ok = all(st["status"] == "PPN_OK" for st in stats)
+    spmv_avg_s = tot["ms_spmv"] / max(tot["n_spmv"], 1) * 1e-3
+    bytes_launch = spmv_bytes(info["n_verts"], info["n_blocks"])
+    achieved = bytes_launch / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
+    traffic = None  # from rocprofv3 FETCH_SIZE/WRITE_SIZE runs; see profiles/
+
+    out = {
+        "metric": "Newton time steps/s (PPN, FP64) + 12x12 eigen-projections/s; p50/p99 step latency (1 GPU)",
+        "value": K / elapsed,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"cube 64^3 cells -> {info['n_tets']} tets / {info['n_verts']} verts, "
+                                f"SNH E log-uniform [1e4,1e6] Pa, nu 0.48, dt 1/30 s, top pushed down "
+                                f"60% over 50 steps; steps 1..{K}; mode {a.mode}"
+                                if a.config == 2 else f"configuration {a.config}, mode {a.mode}"),
+                   "mode": a.mode, "n_tets": info["n_tets"], "n_verts": info["n_verts"],
+                   "n_blocks": info["n_blocks"], "parallelism": "single GPU"},
+        "p50_step_ms": float(np.percentile(lat, 50)),
+        "p99_step_ms": float(np.percentile(lat, 99)),
+        "eig_projections_per_s": (tot["projected"] / (tot["ms_eig"] * 1e-3)) if tot["ms_eig"] > 0 else None,
+        "per_step": {"newton_iters": tot["newton_iters"] / K, "pcg_iters": tot["pcg_iters"] / K,
+                     "solves": tot["solves"] / K, "projected": tot["projected"] / K,
+                     "proj_ratio": tot["projected"] / max(tot["newton_iters"] * info["n_tets"], 1),
+                     "ls_backtracks": tot["ls_backtracks"] / K},
+        "all_steps_converged": ok,
+        "roofline": {"kernel": "k_pcg_spmv (PCG matrix product, FP64 BCSR 3x3)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": spmv_avg_s * 1e6,
+                     "launches": tot["n_spmv"]},
+    }
+    if a.stats_out:
+        with open(a.stats_out, "w") as f:
+            json.dump(stats, f)
+    s.close()
+    if not a.no_cpu_baseline:
+        counts = {"newton_iters": tot["newton_iters"] / K, "pcg_iters": tot["pcg_iters"] / K,
+                  "projected": tot["projected"] / K,
+                  "ls_trials": (tot["newton_iters"] + tot["ls_backtracks"]) / K}
+        out["cpu_baseline"] = cpu_baseline(a.config, counts)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

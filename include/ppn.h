@@ -105,6 +105,9 @@ typedef struct {
   double ms_total;           /* wall time of the step [ms] */
   double ms_eig;             /* time in the eigen-projection kernel [ms] */
   double ms_pcg;             /* time in PCG solves [ms] */
+  double ms_spmv;            /* summed duration of the sampled PCG matrix-product launches,
+                                measured with HIP events when profiling is on (else 0) [ms] */
+  int64_t n_spmv;            /* sampled launches summed in ms_spmv */
 } ppn_step_stats;
 
 /* One record per Newton iteration of the last step (when tracing is on). */
@@ -181,6 +184,10 @@ ppn_status ppn_scene_info(ppn_scene* s, int32_t* n_verts, int32_t* n_tets, int32
 /* Message of the last failing call on this handle (or a global message when
  * s is NULL); valid until the next call on the handle. */
 const char* ppn_last_error(const ppn_scene* s);
+
+/* Kernel timing: when enabled, every 16th PCG matrix-product launch that does work
+ * is bracketed by HIP events on the scene stream and summed into ms_spmv / n_spmv. */
+ppn_status ppn_set_profiling(ppn_scene* s, int32_t enable);
 
 /* ---- tracing ------------------------------------------------------------ */
 /* Record one ppn_iter_record per Newton iteration of subsequent steps, plus

@@ -143,6 +143,9 @@ class Scene:
         self._c(_abi.lib().ppn_set_params(self._h, C.byref(p)))
         return p
 
+    def ppn_set_profiling(self, enable=True):
+        self._c(_abi.lib().ppn_set_profiling(self._h, int(bool(enable))))
+
     def ppn_set_trace(self, enable=True):
         self._c(_abi.lib().ppn_set_trace(self._h, int(bool(enable))))
 

@@ -26,7 +26,8 @@ class ppn_step_stats(C.Structure):
                 ("ls_backtracks", C.c_int32), ("safety_events", C.c_int32), ("converged", C.c_int32),
                 ("ls_fail", C.c_int32), ("skipped_solves", C.c_int32), ("projected", C.c_int64),
                 ("res0_l2", C.c_double), ("res_l2", C.c_double), ("res_inf", C.c_double),
-                ("ms_total", C.c_double), ("ms_eig", C.c_double), ("ms_pcg", C.c_double)]
+                ("ms_total", C.c_double), ("ms_eig", C.c_double), ("ms_pcg", C.c_double),
+                ("ms_spmv", C.c_double), ("n_spmv", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -67,6 +68,7 @@ SIGNATURES = {
     "ppn_scene_info": (C.c_int, [P, ip, ip, ip, i64p, i64p]),
     "ppn_last_error": (C.c_char_p, [P]),
     "ppn_set_trace": (C.c_int, [P, C.c_int32]),
+    "ppn_set_profiling": (C.c_int, [P, C.c_int32]),
     "ppn_trace_count": (C.c_int, [P, ip]),
     "ppn_trace_get": (C.c_int, [P, C.c_int32, C.POINTER(ppn_iter_record), ip]),
     "ppn_eval_gradient": (C.c_int, [P, dp, dp]),

@@ -208,6 +208,12 @@ ppn_status ppn_set_trace(ppn_scene* s, int32_t enable) {
   return PPN_OK;
 }
 
+ppn_status ppn_set_profiling(ppn_scene* s, int32_t enable) {
+  IMPL(s);
+  S.profile_on = enable != 0;
+  return PPN_OK;
+}
+
 ppn_status ppn_trace_count(ppn_scene* s, int32_t* count) {
   IMPL(s);
   if (!count) return bad_handle();

@@ -2,11 +2,13 @@
 //
 // Layout in HBM (all FP64 unless noted):
 //   element data   SoA [k][T]: tets (int32, 4), Dm^-1 rows (9), V, mu, lam
-//   vertex vectors AoS [N][3]: x, x^n, v, xhat, g, dx, r, z, d (2 buffers), q
+//   vertex vectors AoS [N][3]: x, x^n, v, xhat, g, dx, r, q; PCG (z, d) records [2][N][6]
 //   vertex slots   AoS [4T][9]: corner gradient (3) + diagonal block (6)
 //   edge slots     AoS [6T][9]: off-diagonal block, row-major, global orientation
-//   BCSR values    SoA [9][NB] (entry-major, so a 16-lane row group reads
-//                  consecutive doubles per entry), col (int32) [NB], row_ptr [N+1]
+//   BCSR values    sliced ELL: rows in groups of 64 (one wavefront), each group
+//                  padded to its longest row; per slot, the 9 entries of the 64
+//                  rows' blocks are stored entry-major (value (slot*9 + c)*64 + lane),
+//                  so every load of the matrix product is one contiguous 512-byte run
 //   block-Jacobi   SoA [9][N]: inverse of each diagonal block
 #pragma once
 #include <hip/hip_runtime.h>
@@ -35,14 +37,18 @@ struct PcgState {
   int32_t ind;
   int32_t iters;
   int32_t pad;
-  double rr0;
+  double rr0;      // r0^T r0
+  double rz[2];    // r_j^T z_j by iteration parity (beta of the next direction, alpha)
 };
 
 struct Dev {
   int32_t N = 0, T = 0, E = 0;
   int64_t NB = 0;
-  int32_t G = 0;          // workgroups of grid-stride reduction kernels (fixed per scene)
-  int32_t rows_per_wg = 0;  // vertex chunk per workgroup (multiple of 16)
+  int32_t G = 0;          // workgroups of the assembly / reduction kernels (fixed per scene)
+  int32_t rows_per_wg = 0;  // vertex chunk per workgroup of those kernels
+  int32_t Gp = 0;         // workgroups of the PCG kernels (multiple of 8; 256 rows each)
+  int32_t n_groups = 0;   // 64-row groups of the sliced-ELL matrix
+  int64_t n_slots = 0;
   int32_t nD = 0;         // Dirichlet vertices
   double h = 1.0 / 30.0;
   double k_dir = 1e8;
@@ -65,15 +71,16 @@ struct Dev {
   int32_t* vptr = nullptr;       // [N+1]
   int32_t* vslot_elem = nullptr; // [4T]
   int32_t* eptr = nullptr;       // [E+1]
-  int32_t* row_ptr = nullptr;    // [N+1]
-  int32_t* col = nullptr;        // [NB]
-  int32_t* diag_blk = nullptr;   // [N]
-  int32_t* eblk_up = nullptr;    // [E]
-  int32_t* eblk_lo = nullptr;    // [E]
+  int32_t* gslots = nullptr;     // [n_groups] slots of each 64-row group
+  int32_t* goff = nullptr;       // [n_groups + 1] first slot of each group
+  int32_t* col = nullptr;        // [n_slots * 64] column of each (slot, lane)
+  int32_t* diag_blk = nullptr;   // [N] value base index of the diagonal block
+  int32_t* eblk_up = nullptr;    // [E] value base index of block (lo, hi)
+  int32_t* eblk_lo = nullptr;    // [E] value base index of block (hi, lo)
   // slots and matrix
   double* vslots = nullptr;  // [4T][9]
   double* eslots = nullptr;  // [6T][9]
-  double* vals = nullptr;    // [9][NB]
+  double* vals = nullptr;    // [n_slots * 9 * 64], entry c of a block at base + 64 c
   double* pinv = nullptr;    // [9][N]
   uint8_t* spd_ok = nullptr; // [N]
   // Dirichlet
@@ -81,7 +88,8 @@ struct Dev {
   double* xbar = nullptr;      // [nD][3]
   // vectors [N][3]
   double *x = nullptr, *xn = nullptr, *v = nullptr, *xhat = nullptr, *g = nullptr, *dx = nullptr;
-  double *r = nullptr, *z = nullptr, *d0 = nullptr, *d1 = nullptr, *q = nullptr, *xt = nullptr;
+  double *r = nullptr, *q = nullptr, *xt = nullptr;
+  double* zd = nullptr;    // [2][N][6]: (z, d) records by PCG iteration parity
   double* rinf = nullptr;  // [N]
   // selection
   uint8_t* proj = nullptr;  // [T]
@@ -110,7 +118,8 @@ void launch_eig_list(const Dev& D, int32_t n, double eps, hipStream_t st);
 void launch_regather_list(const Dev& D, int32_t n, hipStream_t st);
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st);
 void launch_pcg_init(const Dev& D, hipStream_t st);
-void launch_pcg_iter(const Dev& D, int j, double tol2, int maxit, hipStream_t st);
+void launch_pcg_iter(const Dev& D, int j, double tol2, int maxit, hipStream_t st,
+                     hipEvent_t ev_spmv_start = nullptr, hipEvent_t ev_spmv_stop = nullptr);
 void launch_dx_stats(const Dev& D, hipStream_t st);  // |dx|_inf, g.dx -> scal[0..1]
 void launch_safety_dir(const Dev& D, hipStream_t st);
 void launch_rinf_from(const Dev& D, const double* g, hipStream_t st);  // rinf_i = max_c |g_(i,c)|

@@ -25,17 +25,16 @@ __device__ inline void store_diag(const Dev& D, int i, const double hd[6]) {
   const double di = D.mass[i] / (D.h * D.h) + (D.dir_idx[i] >= 0 ? D.k_dir : 0.0);
   const double a00 = hd[0] + di, a01 = hd[1], a02 = hd[2];
   const double a11 = hd[3] + di, a12 = hd[4], a22 = hd[5] + di;
-  const int64_t NB = D.NB;
-  const int64_t b = D.diag_blk[i];
-  D.vals[0 * NB + b] = a00;
-  D.vals[1 * NB + b] = a01;
-  D.vals[2 * NB + b] = a02;
-  D.vals[3 * NB + b] = a01;
-  D.vals[4 * NB + b] = a11;
-  D.vals[5 * NB + b] = a12;
-  D.vals[6 * NB + b] = a02;
-  D.vals[7 * NB + b] = a12;
-  D.vals[8 * NB + b] = a22;
+  double* vb = D.vals + D.diag_blk[i];
+  vb[0 * kSell] = a00;
+  vb[1 * kSell] = a01;
+  vb[2 * kSell] = a02;
+  vb[3 * kSell] = a01;
+  vb[4 * kSell] = a11;
+  vb[5 * kSell] = a12;
+  vb[6 * kSell] = a02;
+  vb[7 * kSell] = a12;
+  vb[8 * kSell] = a22;
   const double c00 = a11 * a22 - a12 * a12;
   const double c01 = a02 * a12 - a01 * a22;
   const double c02 = a01 * a12 - a02 * a11;
@@ -61,7 +60,7 @@ __device__ inline void store_diag(const Dev& D, int i, const double hd[6]) {
 // Vertex pass of the full assembly: gradient, |g_i|_inf, diagonal block,
 // block-Jacobi inverse, and partial |g|_2^2 and |g|_inf per workgroup.
 __global__ __launch_bounds__(kBlock) void k_assemble_vertex(Dev D) {
-  __shared__ double lds[4];
+  __shared__ double lds[16];
   const int G = D.G;
   const int w = logical_wg(G);
   const int i0 = w * D.rows_per_wg, i1 = min(D.N, i0 + D.rows_per_wg);
@@ -106,14 +105,14 @@ __device__ inline void gather_edge(const Dev& D, int k) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) s[c] += sl[c];
   }
-  const int64_t NB = D.NB;
-  const int64_t bu = D.eblk_up[k], bl = D.eblk_lo[k];
+  double* vu = D.vals + D.eblk_up[k];
+  double* vl = D.vals + D.eblk_lo[k];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D.vals[(3 * r + c) * NB + bu] = s[3 * r + c];
-      D.vals[(3 * c + r) * NB + bl] = s[3 * r + c];
+      vu[(3 * r + c) * kSell] = s[3 * r + c];
+      vl[(3 * c + r) * kSell] = s[3 * r + c];
     }
 }
 
@@ -244,7 +243,7 @@ void launch_select_write(const Dev& D, hipStream_t st) {
 // Reduce partial slots [first, first + n_sum) as sums and the next n_max as
 // maxima into scal[0 .. n_sum + n_max).
 __global__ __launch_bounds__(kBlock) void k_reduce(Dev D, int first, int n_sum, int n_max) {
-  __shared__ double lds[4];
+  __shared__ double lds[16];
   const int G = D.G;
   for (int k = 0; k < n_sum + n_max; ++k) {
     const double* p = D.part + size_t(first + k) * G;
@@ -278,7 +277,7 @@ void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st) {
 
 // |dx|_inf and g.dx -> scal[0] (sum g.dx), scal[1] (max |dx|)
 __global__ __launch_bounds__(kBlock) void k_dx_stats(Dev D) {
-  __shared__ double lds[4];
+  __shared__ double lds[16];
   const int G = D.G;
   const int w = logical_wg(G);
   const int i0 = w * D.rows_per_wg, i1 = min(D.N, i0 + D.rows_per_wg);

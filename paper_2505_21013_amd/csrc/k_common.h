@@ -22,30 +22,35 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Sum over a 256-thread workgroup, returned to every thread.  lds: 4 doubles.
+// Sum over the workgroup (up to 16 wavefronts), returned to every thread; the
+// order is fixed by the workgroup size.  lds: 16 doubles.
 __device__ inline double block_sum(double v, double* lds) {
   v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) lds[w] = v;
   __syncthreads();
-  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  double s = lds[0];
+  for (int k = 1; k < nw; ++k) s += lds[k];
+  return s;
 }
 
 __device__ inline double block_max(double v, double* lds) {
   v = wave_max(v);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) lds[w] = v;
   __syncthreads();
-  return fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+  double s = lds[0];
+  for (int k = 1; k < nw; ++k) s = fmax(s, lds[k]);
+  return s;
 }
 
 // Reduce G per-workgroup partials in a fixed order (every workgroup that calls
 // this gets bit-identical results).
 __device__ inline double reduce_partials(const double* p, int G, double* lds) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < G; i += kBlock) s += p[i];
+  for (int i = threadIdx.x; i < G; i += blockDim.x) s += p[i];
   return block_sum(s, lds);
 }
 

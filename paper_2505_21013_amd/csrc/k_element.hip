@@ -253,7 +253,7 @@ struct Gammas {
 };
 
 __global__ __launch_bounds__(kBlock) void k_energy_diff(Dev D, int ng, Gammas gm) {
-  __shared__ double lds[4];
+  __shared__ double lds[16];
   const int G = D.G;
   const int wg = blockIdx.x;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};

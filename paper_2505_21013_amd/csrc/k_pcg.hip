@@ -3,24 +3,36 @@
 // (Sec. 4.1, Linear Solvers), zero initial guess, and |r| <= rtol |r0|.
 //
 // One iteration is two kernels whose control scalars stay on the device:
-//   spmv   : beta from the r^T z partials, the new direction d = z + beta d_old
-//            (formed on the fly for every gathered column), q = H d and
-//            partials of d^T q;
-//   update : alpha = r^T z / d^T q, x += alpha d, r -= alpha q, z = P^-1 r and
-//            partials of r^T r and r^T z.
+//   spmv   : beta = r_j^T z_j / r_{j-1}^T z_{j-1}, the new direction
+//            d_j = z_j + beta d_{j-1}, q = H d_j and partials of d_j^T q;
+//   update : alpha = r_j^T z_j / d_j^T q, x += alpha d_j, r -= alpha q,
+//            z = P^-1 r and partials of r^T r and r^T z.
 // Every workgroup reduces the same partials in the same order, so all of them
 // take the same stop decision; workgroup 0 records it in PcgState and later
 // launches return at once.  The host only polls PcgState every few iterations.
+// No fences or grid barriers are used: on a multi-XCD part a device-scope
+// fence writes back the whole L2, while the kernel boundary does it once.
 //
-// SpMV mapping: 16 lanes per block row (rows have at most 15 blocks in a
-// Kuhn-split grid; longer rows loop), 16 rows per 256-thread workgroup step;
-// the SoA value layout makes each of the 9 value loads of a lane group one
-// contiguous run.  Workgroups own contiguous row chunks, grouped per XCD.
+// Data: zd[2][N][6] holds (z, d) per vertex in 48-byte records, double-buffered
+// by iteration parity: the product of iteration j gathers (z_j, d_{j-1}) from
+// zd[j&1] with three 16-byte loads per column and writes d_j into zd[(j+1)&1];
+// the update writes z_{j+1} next to it.
+//
+// The product is formed as H z + beta H d_old so that the streaming loop does
+// not wait for this iteration's reductions.
+//
+// Matrix product: one row per lane, one 64-row sliced-ELL group per wavefront
+// (uniform slot loop; every column-index and block-entry load is one contiguous
+// 256 / 512-byte run), 4 groups per 256-thread workgroup, workgroups mapped to
+// contiguous row ranges per XCD.
 #include <hip/hip_runtime.h>
 
 #include "k_common.h"
+#include "topology.h"
 
 namespace ppn {
+
+constexpr int kPcgBlock = 256;  // threads per PCG workgroup: 4 groups of 64 rows
 
 __device__ inline void pcg_finish(const Dev& D, int ind, int iters) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -30,15 +42,15 @@ __device__ inline void pcg_finish(const Dev& D, int ind, int iters) {
   }
 }
 
-// r = -g, x = 0, z = P^-1 r; partials of r^T r, r^T z and the count of
-// diagonal blocks failing Sylvester's criterion.
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Dev D) {
-  __shared__ double lds[4];
-  const int G = D.G, N = D.N;
-  const int w = logical_wg(G);
-  const int i0 = w * D.rows_per_wg, i1 = min(N, i0 + D.rows_per_wg);
+// r = -g, x = 0, z = P^-1 r into zd[0]; partials of r^T r, r^T z and the
+// count of diagonal blocks failing Sylvester's criterion.
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D) {
+  __shared__ double lds[16];
+  const int Gp = D.Gp, N = D.N;
+  const int w = logical_wg(Gp);
+  const int i = w * kPcgBlock + threadIdx.x;
   double rr = 0.0, rz = 0.0, bad = 0.0;
-  for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
+  if (i < N) {
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -50,19 +62,19 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Dev D) {
     for (int c = 0; c < 3; ++c) {
       const double zc = D.pinv[(3 * c) * N + i] * r[0] + D.pinv[(3 * c + 1) * N + i] * r[1] +
                         D.pinv[(3 * c + 2) * N + i] * r[2];
-      D.z[3 * i + c] = zc;
+      D.zd[6 * size_t(i) + c] = zc;
       rz += r[c] * zc;
       rr += r[c] * r[c];
     }
-    bad += D.spd_ok[i] ? 0.0 : 1.0;
+    bad = D.spd_ok[i] ? 0.0 : 1.0;
   }
   rr = block_sum(rr, lds);
   rz = block_sum(rz, lds);
   bad = block_sum(bad, lds);
   if (threadIdx.x == 0) {
-    D.part[kPartRR * G + w] = rr;
-    D.part[kPartRZ0 * G + w] = rz;
-    D.part[kPartSpd * G + w] = bad;
+    D.part[kPartRR * Gp + w] = rr;
+    D.part[kPartRZ0 * Gp + w] = rz;
+    D.part[kPartSpd * Gp + w] = bad;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     D.pcg->done = 0;
@@ -71,113 +83,189 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Dev D) {
   }
 }
 
+// q_i = sum over the row's slots of B d_col.  kZD: d_col = z_col + beta dold_col
+// gathered from interleaved records; otherwise d_col is read from a plain [N][3] vector.
+template <bool kZD, bool kDir>
+__device__ __forceinline__ void sell_row_product(const Dev& D, const double* __restrict__ src,
+                                                 double beta, int g, int l, double& q0, double& q1,
+                                                 double& q2) {
+  const int S = D.gslots[g];
+  const int base = D.goff[g];
+  q0 = q1 = q2 = 0.0;
+#pragma unroll 4
+  for (int s = 0; s < S; ++s) {
+    const int slot = base + s;
+    const int c = D.col[slot * kSell + l];
+    double d0, d1, d2;
+    if (kZD) {
+      const double2* p = reinterpret_cast<const double2*>(src + 6 * size_t(c));
+      const double2 a = p[0], b = p[1], e = p[2];
+      d0 = a.x;
+      d1 = a.y;
+      d2 = b.x;
+      if (kDir) {
+        d0 += beta * b.y;
+        d1 += beta * e.x;
+        d2 += beta * e.y;
+      }
+    } else {
+      d0 = src[3 * c];
+      d1 = src[3 * c + 1];
+      d2 = src[3 * c + 2];
+    }
+    const double* v = D.vals + size_t(slot) * (9 * kSell) + l;
+    q0 += v[0 * kSell] * d0 + v[1 * kSell] * d1 + v[2 * kSell] * d2;
+    q1 += v[3 * kSell] * d0 + v[4 * kSell] * d1 + v[5 * kSell] * d2;
+    q2 += v[6 * kSell] * d0 + v[7 * kSell] * d1 + v[8 * kSell] * d2;
+  }
+}
+
+// Split product over the gathered (z, d_old) records: qz = H z and qd = H d_old,
+// so that q = H (z + beta d_old) = qz + beta qd needs beta only at the end.
+__device__ __forceinline__ void sell_row_product_split(const Dev& D, const double* __restrict__ zd,
+                                                       bool with_d, int g, int l, double qz[3],
+                                                       double qd[3]) {
+  const int S = D.gslots[g];
+  const int base = D.goff[g];
+  qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = 0.0;
+#pragma unroll 4
+  for (int s = 0; s < S; ++s) {
+    const int slot = base + s;
+    const int c = D.col[slot * kSell + l];
+    const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
+    const double2 a = p[0], b = p[1];
+    const double* v = D.vals + size_t(slot) * (9 * kSell) + l;
+    double w[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) w[e] = v[e * kSell];
+    qz[0] += w[0] * a.x + w[1] * a.y + w[2] * b.x;
+    qz[1] += w[3] * a.x + w[4] * a.y + w[5] * b.x;
+    qz[2] += w[6] * a.x + w[7] * a.y + w[8] * b.x;
+    if (with_d) {
+      const double2 e = p[2];
+      qd[0] += w[0] * b.y + w[1] * e.x + w[2] * e.y;
+      qd[1] += w[3] * b.y + w[4] * e.x + w[5] * e.y;
+      qd[2] += w[6] * b.y + w[7] * e.x + w[8] * e.y;
+    }
+  }
+}
+
+// The streaming loop does not depend on this iteration's scalars: the partial
+// sums that decide beta and the stop test are loaded first, the product runs,
+// and only then are the partials combined (their load latency hides under the loop).
 template <bool kFirst>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Dev D, int j, double tol2, int maxit) {
-  __shared__ double lds[4];
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, int j, double tol2, int maxit) {
+  __shared__ double lds[16];
   if (D.pcg->done) return;
-  const int G = D.G;
-  const double* dold = (j & 1) ? D.d0 : D.d1;
-  double* dnew = (j & 1) ? D.d1 : D.d0;
+  const int Gp = D.Gp;
+  const double* zcur = D.zd + ((j & 1) ? 6 * size_t(D.N) : 0);
+  double* znext = D.zd + ((j & 1) ? 0 : 6 * size_t(D.N));
+  const double* pa = D.part + kPartRR * Gp;
+  const double* pb = D.part + ((j & 1) ? kPartRZ1 : kPartRZ0) * Gp;
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+  for (int k = threadIdx.x; k < Gp; k += kPcgBlock) {
+    sa += pa[k];
+    sb += pb[k];
+    if (kFirst) sc += D.part[kPartSpd * Gp + k];
+  }
+  const int w = logical_wg(Gp);
+  const int i = w * kPcgBlock + threadIdx.x;
+  const int g = i / kSell, l = i % kSell;
+  double qz[3] = {0, 0, 0}, qd[3] = {0, 0, 0};
+  if (g < D.n_groups) sell_row_product_split(D, zcur, !kFirst, g, l, qz, qd);
+
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  if (kFirst) sc = wave_sum(sc);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    lds[wv] = sa;
+    lds[4 + wv] = sb;
+    lds[8 + wv] = sc;
+  }
+  __syncthreads();
+  const double rr = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  const double rz = ((lds[4] + lds[5]) + lds[6]) + lds[7];
+  const double bad = ((lds[8] + lds[9]) + lds[10]) + lds[11];
   double beta = 0.0;
   if (kFirst) {
-    const double rr0 = reduce_partials(D.part + kPartRR * G, G, lds);
-    const double rz0 = reduce_partials(D.part + kPartRZ0 * G, G, lds);
-    const double bad = reduce_partials(D.part + kPartSpd * G, G, lds);
     if (bad > 0.0) { pcg_finish(D, 1, 0); return; }
-    if (rr0 == 0.0) { pcg_finish(D, 0, 0); return; }
-    if (rz0 <= 0.0) { pcg_finish(D, 1, 0); return; }
-    if (blockIdx.x == 0 && threadIdx.x == 0) D.pcg->rr0 = rr0;
+    if (rr == 0.0) { pcg_finish(D, 0, 0); return; }
+    if (rz <= 0.0) { pcg_finish(D, 1, 0); return; }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      D.pcg->rr0 = rr;
+      D.pcg->rz[0] = rz;
+    }
   } else {
-    const double rr = reduce_partials(D.part + kPartRR * G, G, lds);
-    const double rz = reduce_partials(D.part + ((j & 1) ? kPartRZ1 : kPartRZ0) * G, G, lds);
     if (rr <= tol2 * D.pcg->rr0) { pcg_finish(D, 0, j); return; }
     if (rz <= 0.0) { pcg_finish(D, 1, j); return; }
     if (j >= maxit) { pcg_finish(D, 0, j); return; }
-    const double rzo = reduce_partials(D.part + ((j & 1) ? kPartRZ0 : kPartRZ1) * G, G, lds);
-    beta = rz / rzo;
+    beta = rz / D.pcg->rz[(j - 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) D.pcg->rz[j & 1] = rz;
   }
-  const int w = logical_wg(G);
-  const int i0 = w * D.rows_per_wg, i1 = min(D.N, i0 + D.rows_per_wg);
-  const int lane = threadIdx.x & 15;
-  const int64_t NB = D.NB;
   double kap = 0.0;
-  for (int ib = i0; ib < i1; ib += kBlock / 16) {
-    const int i = ib + (threadIdx.x >> 4);
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
-    if (i < i1) {
-      const int k0 = D.row_ptr[i], k1 = D.row_ptr[i + 1];
-      for (int k = k0 + lane; k < k1; k += 16) {
-        const int c = D.col[k];
-        double d0, d1, d2;
-        if (kFirst) {
-          d0 = D.z[3 * c];
-          d1 = D.z[3 * c + 1];
-          d2 = D.z[3 * c + 2];
-        } else {
-          d0 = D.z[3 * c] + beta * dold[3 * c];
-          d1 = D.z[3 * c + 1] + beta * dold[3 * c + 1];
-          d2 = D.z[3 * c + 2] + beta * dold[3 * c + 2];
-        }
-        q0 += D.vals[0 * NB + k] * d0 + D.vals[1 * NB + k] * d1 + D.vals[2 * NB + k] * d2;
-        q1 += D.vals[3 * NB + k] * d0 + D.vals[4 * NB + k] * d1 + D.vals[5 * NB + k] * d2;
-        q2 += D.vals[6 * NB + k] * d0 + D.vals[7 * NB + k] * d1 + D.vals[8 * NB + k] * d2;
-      }
+  if (i < D.N) {
+    const double2* p = reinterpret_cast<const double2*>(zcur + 6 * size_t(i));
+    const double2 a = p[0], b = p[1], e = p[2];
+    double dn0 = a.x, dn1 = a.y, dn2 = b.x;
+    double q0 = qz[0], q1 = qz[1], q2 = qz[2];
+    if (!kFirst) {
+      dn0 += beta * b.y;
+      dn1 += beta * e.x;
+      dn2 += beta * e.y;
+      q0 += beta * qd[0];
+      q1 += beta * qd[1];
+      q2 += beta * qd[2];
     }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-      q0 += __shfl_xor(q0, o, 16);
-      q1 += __shfl_xor(q1, o, 16);
-      q2 += __shfl_xor(q2, o, 16);
-    }
-    if (i < i1 && lane == 0) {
-      double dn0, dn1, dn2;
-      if (kFirst) {
-        dn0 = D.z[3 * i];
-        dn1 = D.z[3 * i + 1];
-        dn2 = D.z[3 * i + 2];
-      } else {
-        dn0 = D.z[3 * i] + beta * dold[3 * i];
-        dn1 = D.z[3 * i + 1] + beta * dold[3 * i + 1];
-        dn2 = D.z[3 * i + 2] + beta * dold[3 * i + 2];
-      }
-      dnew[3 * i] = dn0;
-      dnew[3 * i + 1] = dn1;
-      dnew[3 * i + 2] = dn2;
-      D.q[3 * i] = q0;
-      D.q[3 * i + 1] = q1;
-      D.q[3 * i + 2] = q2;
-      kap += dn0 * q0 + dn1 * q1 + dn2 * q2;
-    }
+    double* o = znext + 6 * size_t(i) + 3;
+    o[0] = dn0;
+    o[1] = dn1;
+    o[2] = dn2;
+    D.q[3 * i] = q0;
+    D.q[3 * i + 1] = q1;
+    D.q[3 * i + 2] = q2;
+    kap = dn0 * q0 + dn1 * q1 + dn2 * q2;
   }
   kap = block_sum(kap, lds);
-  if (threadIdx.x == 0) D.part[kPartKappa * G + w] = kap;
+  if (threadIdx.x == 0) D.part[kPartKappa * Gp + w] = kap;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Dev D, int j) {
-  __shared__ double lds[4];
+// The row's inputs are loaded before the d^T q partials are combined, so both
+// latencies overlap.
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, int j) {
+  __shared__ double lds[16];
   if (D.pcg->done) return;
-  const int G = D.G, N = D.N;
-  const double kap = reduce_partials(D.part + kPartKappa * G, G, lds);
-  if (kap <= 0.0) { pcg_finish(D, 1, j + 1); return; }
-  const double rz = reduce_partials(D.part + ((j & 1) ? kPartRZ1 : kPartRZ0) * G, G, lds);
-  const double alpha = rz / kap;
-  const double* d = (j & 1) ? D.d1 : D.d0;
-  const int w = logical_wg(G);
-  const int i0 = w * D.rows_per_wg, i1 = min(N, i0 + D.rows_per_wg);
-  double rr = 0.0, rzn = 0.0;
-  for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-    double r[3];
+  const int Gp = D.Gp, N = D.N;
+  double* znext = D.zd + ((j & 1) ? 0 : 6 * size_t(N));
+  const int w = logical_wg(Gp);
+  const int i = w * kPcgBlock + threadIdx.x;
+  double d[3] = {0, 0, 0}, q[3] = {0, 0, 0}, r[3] = {0, 0, 0}, x[3] = {0, 0, 0}, P[9];
+  if (i < N) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D.dx[3 * i + c] += alpha * d[3 * i + c];
-      r[c] = D.r[3 * i + c] - alpha * D.q[3 * i + c];
+      d[c] = znext[6 * size_t(i) + 3 + c];
+      q[c] = D.q[3 * i + c];
+      r[c] = D.r[3 * i + c];
+      x[c] = D.dx[3 * i + c];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) P[k] = D.pinv[k * N + i];
+  }
+  const double kap = reduce_partials(D.part + kPartKappa * Gp, Gp, lds);
+  if (kap <= 0.0) { pcg_finish(D, 1, j + 1); return; }
+  const double alpha = D.pcg->rz[j & 1] / kap;
+  double rr = 0.0, rzn = 0.0;
+  if (i < N) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.dx[3 * i + c] = x[c] + alpha * d[c];
+      r[c] -= alpha * q[c];
       D.r[3 * i + c] = r[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double zc = D.pinv[(3 * c) * N + i] * r[0] + D.pinv[(3 * c + 1) * N + i] * r[1] +
-                        D.pinv[(3 * c + 2) * N + i] * r[2];
-      D.z[3 * i + c] = zc;
+      const double zc = P[3 * c] * r[0] + P[3 * c + 1] * r[1] + P[3 * c + 2] * r[2];
+      znext[6 * size_t(i) + c] = zc;
       rzn += r[c] * zc;
       rr += r[c] * r[c];
     }
@@ -185,56 +273,43 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Dev D, int j) {
   rr = block_sum(rr, lds);
   rzn = block_sum(rzn, lds);
   if (threadIdx.x == 0) {
-    D.part[kPartRR * G + w] = rr;
-    D.part[((j & 1) ? kPartRZ0 : kPartRZ1) * G + w] = rzn;
+    D.part[kPartRR * Gp + w] = rr;
+    D.part[((j & 1) ? kPartRZ0 : kPartRZ1) * Gp + w] = rzn;
   }
 }
 
-void launch_pcg_init(const Dev& D, hipStream_t st) { k_pcg_init<<<D.G, kBlock, 0, st>>>(D); }
+void launch_pcg_init(const Dev& D, hipStream_t st) {
+  k_pcg_init<<<D.Gp, kPcgBlock, 0, st>>>(D);
+}
 
-void launch_pcg_iter(const Dev& D, int j, double tol2, int maxit, hipStream_t st) {
+void launch_pcg_iter(const Dev& D, int j, double tol2, int maxit, hipStream_t st,
+                     hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
+  if (ev_spmv_start) (void)hipEventRecord(ev_spmv_start, st);
   if (j == 0)
-    k_pcg_spmv<true><<<D.G, kBlock, 0, st>>>(D, j, tol2, maxit);
+    k_pcg_spmv<true><<<D.Gp, kPcgBlock, 0, st>>>(D, j, tol2, maxit);
   else
-    k_pcg_spmv<false><<<D.G, kBlock, 0, st>>>(D, j, tol2, maxit);
-  k_pcg_update<<<D.G, kBlock, 0, st>>>(D, j);
+    k_pcg_spmv<false><<<D.Gp, kPcgBlock, 0, st>>>(D, j, tol2, maxit);
+  if (ev_spmv_stop) (void)hipEventRecord(ev_spmv_stop, st);
+  k_pcg_update<<<D.Gp, kPcgBlock, 0, st>>>(D, j);
 }
 
 // Plain q = H d (parity tests and benchmarks).
-__global__ __launch_bounds__(kBlock) void k_spmv_plain(Dev D, const double* d, double* q) {
-  const int G = D.G;
-  const int w = logical_wg(G);
-  const int i0 = w * D.rows_per_wg, i1 = min(D.N, i0 + D.rows_per_wg);
-  const int lane = threadIdx.x & 15;
-  const int64_t NB = D.NB;
-  for (int ib = i0; ib < i1; ib += kBlock / 16) {
-    const int i = ib + (threadIdx.x >> 4);
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
-    if (i < i1) {
-      for (int k = D.row_ptr[i] + lane; k < D.row_ptr[i + 1]; k += 16) {
-        const int c = D.col[k];
-        const double d0 = d[3 * c], d1 = d[3 * c + 1], d2 = d[3 * c + 2];
-        q0 += D.vals[0 * NB + k] * d0 + D.vals[1 * NB + k] * d1 + D.vals[2 * NB + k] * d2;
-        q1 += D.vals[3 * NB + k] * d0 + D.vals[4 * NB + k] * d1 + D.vals[5 * NB + k] * d2;
-        q2 += D.vals[6 * NB + k] * d0 + D.vals[7 * NB + k] * d1 + D.vals[8 * NB + k] * d2;
-      }
-    }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-      q0 += __shfl_xor(q0, o, 16);
-      q1 += __shfl_xor(q1, o, 16);
-      q2 += __shfl_xor(q2, o, 16);
-    }
-    if (i < i1 && lane == 0) {
-      q[3 * i] = q0;
-      q[3 * i + 1] = q1;
-      q[3 * i + 2] = q2;
-    }
+__global__ __launch_bounds__(kPcgBlock) void k_spmv_plain(Dev D, const double* d, double* q) {
+  const int w = logical_wg(D.Gp);
+  const int i = w * kPcgBlock + threadIdx.x;
+  const int g = i / kSell, l = i % kSell;
+  if (g >= D.n_groups) return;
+  double q0, q1, q2;
+  sell_row_product<false, false>(D, d, 0.0, g, l, q0, q1, q2);
+  if (i < D.N) {
+    q[3 * i] = q0;
+    q[3 * i + 1] = q1;
+    q[3 * i + 2] = q2;
   }
 }
 
 void launch_spmv_plain(const Dev& D, const double* d, double* q, hipStream_t st) {
-  k_spmv_plain<<<D.G, kBlock, 0, st>>>(D, d, q);
+  k_spmv_plain<<<D.Gp, kPcgBlock, 0, st>>>(D, d, q);
 }
 
 }  // namespace ppn

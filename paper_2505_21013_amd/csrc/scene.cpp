@@ -23,6 +23,10 @@ namespace ppn {
 
 static void fail(const std::string& m, ppn_status c = PPN_ERR_ARG) { throw HipError{m, c}; }
 
+// Every kProfileEvery-th PCG matrix product is bracketed by timing events when
+// profiling is on (sampling keeps the events from perturbing the launch stream).
+constexpr int kProfileEvery = 16;
+
 void params_defaults(ppn_params* p) {
   std::memset(p, 0, sizeof(*p));
   p->alpha = 0.5;
@@ -59,6 +63,7 @@ Scene::~Scene() {
   if (hint_) (void)hipHostFree(hint_);
   for (auto& e : ev_)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : prof_ev_) (void)hipEventDestroy(e);
   if (own_stream_ && st_) (void)hipStreamDestroy(st_);
 }
 
@@ -110,6 +115,11 @@ void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* t
     D.G = G;
     D.rows_per_wg = (((N + G - 1) / G) + 15) / 16 * 16;
     D.n_sel_wg = (T + kBlock - 1) / kBlock;
+    // PCG kernels: one row per thread, one 64-row group per wavefront; up to 8
+    // wavefronts per workgroup once there are enough groups to keep every CU busy.
+    D.n_groups = topo_.n_groups;
+    D.n_slots = topo_.n_slots;
+    D.Gp = ((D.n_groups + 3) / 4 + 7) / 8 * 8;
     D.h = D_.h;
     D.k_dir = prm_.k_dirichlet;
     std::memcpy(D.grav, D_.grav, sizeof(D.grav));
@@ -130,27 +140,28 @@ void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* t
     D_.vptr = alloc<int32_t>(n + 1);
     D_.vslot_elem = alloc<int32_t>(4 * m);
     D_.eptr = alloc<int32_t>(size_t(D_.E) + 1);
-    D_.row_ptr = alloc<int32_t>(n + 1);
-    D_.col = alloc<int32_t>(size_t(D_.NB));
+    D_.gslots = alloc<int32_t>(size_t(D_.n_groups));
+    D_.goff = alloc<int32_t>(size_t(D_.n_groups) + 1);
+    D_.col = alloc<int32_t>(size_t(D_.n_slots) * kSell);
     D_.diag_blk = alloc<int32_t>(n);
     D_.eblk_up = alloc<int32_t>(size_t(D_.E));
     D_.eblk_lo = alloc<int32_t>(size_t(D_.E));
     D_.vslots = alloc<double>(4 * m * 9);
     D_.eslots = alloc<double>(6 * m * 9);
-    D_.vals = alloc<double>(9 * size_t(D_.NB));
+    D_.vals = alloc<double>(size_t(D_.n_slots) * 9 * kSell);
     D_.pinv = alloc<double>(9 * n);
     D_.spd_ok = alloc<uint8_t>(n);
     D_.dir_idx = alloc<int32_t>(n);
     D_.xbar = alloc<double>(3 * n);
-    double** vecs[] = {&D_.x, &D_.xn, &D_.v, &D_.xhat, &D_.g, &D_.dx,
-                       &D_.r, &D_.z,  &D_.d0, &D_.d1,  &D_.q, &D_.xt};
+    double** vecs[] = {&D_.x, &D_.xn, &D_.v, &D_.xhat, &D_.g, &D_.dx, &D_.r, &D_.q, &D_.xt};
     for (double** p : vecs) *p = alloc<double>(3 * n);
+    D_.zd = alloc<double>(12 * n);
     D_.rinf = alloc<double>(n);
     D_.proj = alloc<uint8_t>(m);
     D_.sel = alloc<uint8_t>(m);
     D_.list = alloc<int32_t>(m);
     D_.sel_cnt = alloc<int32_t>(size_t(D_.n_sel_wg) + 1);
-    D_.part = alloc<double>(size_t(kPartCount) * G);
+    D_.part = alloc<double>(size_t(kPartCount) * std::max(G, D_.Gp));
     D_.scal = alloc<double>(16);
     D_.pcg = alloc<PcgState>(1);
     D_.flag = alloc<int32_t>(4);
@@ -171,11 +182,14 @@ void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* t
     up(D_.vptr, topo_.vptr.data(), (n + 1) * 4);
     up(D_.vslot_elem, topo_.vslot_elem.data(), 4 * m * 4);
     up(D_.eptr, topo_.eptr.data(), (size_t(D_.E) + 1) * 4);
-    up(D_.row_ptr, topo_.row_ptr.data(), (n + 1) * 4);
-    up(D_.col, topo_.col.data(), size_t(D_.NB) * 4);
-    up(D_.diag_blk, topo_.diag_blk.data(), n * 4);
-    up(D_.eblk_up, topo_.eblk_up.data(), size_t(D_.E) * 4);
-    up(D_.eblk_lo, topo_.eblk_lo.data(), size_t(D_.E) * 4);
+    up(D_.gslots, topo_.gslots.data(), size_t(D_.n_groups) * 4);
+    up(D_.goff, topo_.goff.data(), (size_t(D_.n_groups) + 1) * 4);
+    up(D_.col, topo_.sell_col.data(), size_t(D_.n_slots) * kSell * 4);
+    up(D_.diag_blk, topo_.diag_base.data(), n * 4);
+    up(D_.eblk_up, topo_.eup_base.data(), size_t(D_.E) * 4);
+    up(D_.eblk_lo, topo_.elo_base.data(), size_t(D_.E) * 4);
+    // padding slots of the sliced-ELL values stay zero for the life of the scene
+    HIPCHK(hipMemsetAsync(D_.vals, 0, size_t(D_.n_slots) * 9 * kSell * 8, st_));
     X_.assign(rest, rest + 3 * n);
     if (E_.size() != m) {
       const double e0 = E_.empty() ? 1e5 : E_[0], n0 = nu_.empty() ? 0.45 : nu_[0];
@@ -361,11 +375,26 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
   LAUNCHCHK();
   const double tol2 = prm_.pcg_rtol * prm_.pcg_rtol;
   const int maxit = prm_.pcg_maxit;
+  // Iterations are enqueued in chunks; the status of chunk c-1 is read while
+  // chunk c runs, so launches past convergence (which return at once) are at
+  // most two chunks.
   int j = 0, chunk = 8, slot = 0;
   bool pending = false;
   while (j <= maxit) {
     const int jend = std::min(j + chunk, maxit + 1);
-    for (; j < jend; ++j) launch_pcg_iter(D_, j, tol2, maxit, st_);
+    if (profile_on)
+      while (prof_ev_.size() < 2 * size_t(jend / kProfileEvery + 1)) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        prof_ev_.push_back(e);
+      }
+    for (; j < jend; ++j) {
+      if (profile_on && j % kProfileEvery == 0)
+        launch_pcg_iter(D_, j, tol2, maxit, st_, prof_ev_[2 * (j / kProfileEvery)],
+                        prof_ev_[2 * (j / kProfileEvery) + 1]);
+      else
+        launch_pcg_iter(D_, j, tol2, maxit, st_);
+    }
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(&hpcg_[slot], D_.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, st_));
     HIPCHK(hipEventRecord(ev_[slot], st_));
@@ -375,13 +404,25 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
     }
     pending = true;
     slot ^= 1;
-    chunk = std::min(chunk * 2, 64);
+    chunk = std::min(chunk * 2, 32);
   }
   HIPCHK(hipMemcpyAsync(&hpcg_[2], D_.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, st_));
   sync();
   if (!hpcg_[2].done) fail("PCG ended without a decision", PPN_ERR_DEVICE);
   ind = hpcg_[2].ind;
   iters = hpcg_[2].iters;
+  if (profile_on) {
+    // Sampled launches j = 0, 16, 32, ... < iters carried out a full product
+    // (launches at j >= iters returned at once).  j = 0 is the first-direction
+    // variant and is skipped.
+    for (int k = kProfileEvery; k < iters; k += kProfileEvery) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, prof_ev_[2 * (k / kProfileEvery)],
+                                 prof_ev_[2 * (k / kProfileEvery) + 1]));
+      last_stats.ms_spmv += ms;
+      last_stats.n_spmv++;
+    }
+  }
   last_stats.ms_pcg +=
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -605,11 +646,11 @@ void Scene::eval_hessian(const double* x, const uint8_t* mask, int32_t* row_ptr,
   project_mask(mask);
   if (vals) {
     const size_t NB = size_t(D_.NB);
-    std::vector<double> soa(9 * NB);
-    HIPCHK(hipMemcpyAsync(soa.data(), D_.vals, soa.size() * 8, hipMemcpyDeviceToHost, st_));
+    std::vector<double> sell(size_t(D_.n_slots) * 9 * kSell);
+    HIPCHK(hipMemcpyAsync(sell.data(), D_.vals, sell.size() * 8, hipMemcpyDeviceToHost, st_));
     sync();
     for (size_t b = 0; b < NB; ++b)
-      for (int c = 0; c < 9; ++c) vals[9 * b + c] = soa[c * NB + b];
+      for (int c = 0; c < 9; ++c) vals[9 * b + c] = sell[size_t(topo_.csr_base[b]) + size_t(c) * kSell];
   }
   if (row_ptr) std::copy(topo_.row_ptr.begin(), topo_.row_ptr.end(), row_ptr);
   if (col) std::copy(topo_.col.begin(), topo_.col.end(), col);

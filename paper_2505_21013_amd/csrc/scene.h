@@ -55,6 +55,7 @@ class Scene {
   ppn_step_stats last_stats{};
   std::string last_error;
   bool trace_on = false;
+  bool profile_on = false;
   std::vector<ppn_iter_record> trace;
   std::vector<std::vector<int32_t>> trace_ids;
 
@@ -92,6 +93,7 @@ class Scene {
   PcgState* hpcg_ = nullptr;
   int32_t* hint_ = nullptr;
   hipEvent_t ev_[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> prof_ev_;  // start/stop pairs of profiled matrix-product launches
   bool all_projected_ = false;
   int32_t n_projected_ = 0;
 };

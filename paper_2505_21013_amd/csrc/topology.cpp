@@ -124,6 +124,43 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
     t.col[bl] = lo;
     t.eblk_lo[k] = bl;
   }
+
+  // ---- sliced-ELL layout of the same blocks
+  t.n_groups = (N + kSell - 1) / kSell;
+  t.gslots.assign(t.n_groups, 0);
+  t.goff.assign(t.n_groups + 1, 0);
+  for (int32_t i = 0; i < N; ++i)
+    t.gslots[i / kSell] = std::max(t.gslots[i / kSell], t.row_ptr[i + 1] - t.row_ptr[i]);
+  for (int32_t g = 0; g < t.n_groups; ++g) t.goff[g + 1] = t.goff[g] + t.gslots[g];
+  t.n_slots = t.goff[t.n_groups];
+  if (t.n_slots * 9 * kSell >= (int64_t(1) << 31)) {
+    err = "matrix too large for 32-bit sliced-ELL indices";
+    return false;
+  }
+  t.sell_col.assign(size_t(t.n_slots) * kSell, 0);
+  t.csr_base.resize(size_t(t.n_blocks));
+  for (int32_t g = 0; g < t.n_groups; ++g)
+    for (int32_t l = 0; l < kSell; ++l) {
+      const int32_t i = g * kSell + l;
+      for (int32_t s = 0; s < t.gslots[g]; ++s) {
+        const int64_t slot = t.goff[g] + s;
+        int32_t c = i < N ? i : 0;
+        if (i < N && s < t.row_ptr[i + 1] - t.row_ptr[i]) {
+          const int32_t k = t.row_ptr[i] + s;
+          c = t.col[k];
+          t.csr_base[k] = int32_t(slot * 9 * kSell + l);
+        }
+        t.sell_col[size_t(slot) * kSell + l] = c;
+      }
+    }
+  t.diag_base.resize(N);
+  for (int32_t i = 0; i < N; ++i) t.diag_base[i] = t.csr_base[t.diag_blk[i]];
+  t.eup_base.resize(E);
+  t.elo_base.resize(E);
+  for (int32_t k = 0; k < E; ++k) {
+    t.eup_base[k] = t.csr_base[t.eblk_up[k]];
+    t.elo_base[k] = t.csr_base[t.eblk_lo[k]];
+  }
   return true;
 }
 

@@ -44,7 +44,25 @@ struct Topology {
   std::vector<int32_t> diag_blk;   // [N]
   std::vector<int32_t> eblk_up;    // [E] block (lo, hi)
   std::vector<int32_t> eblk_lo;    // [E] block (hi, lo)
+
+  // Sliced-ELL copy of the pattern used by the device (see kSell below): rows
+  // in groups of 64, group g padded to gslots[g] = its longest row; slot s of
+  // group g starts at goff[g] + s.  Entry c of the block in slot s, row lane l
+  // lives at value index (goff[g] + s) * 9 * 64 + c * 64 + l; its column at
+  // (goff[g] + s) * 64 + l.  Padding slots hold column = the row itself and
+  // zero values.
+  int32_t n_groups = 0;
+  int64_t n_slots = 0;              // sum of gslots (block rows of 64)
+  std::vector<int32_t> gslots;      // [n_groups]
+  std::vector<int32_t> goff;        // [n_groups + 1]
+  std::vector<int32_t> sell_col;    // [n_slots * 64]
+  std::vector<int32_t> csr_base;    // [NB] value base index of each CSR block
+  std::vector<int32_t> diag_base;   // [N]
+  std::vector<int32_t> eup_base;    // [E]
+  std::vector<int32_t> elo_base;    // [E]
 };
+
+constexpr int kSell = 64;  // rows per sliced-ELL group (one wavefront)
 
 // Builds the topology from tets [T][4] (AoS, 0-based).  Returns false and sets
 // err when an index is out of range or an element repeats a vertex.

@@ -97,9 +97,13 @@ def _face(X, axis, value, atol=1e-12):
 
 
 def cube_jitter(n=6, E=1e5, nu=0.45, rho=1000.0, dt=1.0 / 60.0, jitter=0.05, seed=0,
-                n_steps=20) -> Scene:
+                n_steps=20, newton_rel_tol=1e-6) -> Scene:
     """Small parity scene: unit cube of n^3 cells, bottom face pinned to rest,
-    gravity, every initial vertex jittered by U(-jitter*cell, +jitter*cell)."""
+    gravity, every initial vertex jittered by U(-jitter*cell, +jitter*cell).
+
+    Newton stops once the step is below ``newton_rel_tol`` of the body's size
+    (the rest bounding-box diagonal), expressed as the velocity criterion
+    |dx|_inf / dt < newton_rel_tol * diag / dt."""
     X, tets = kuhn_grid(n, n, n)
     cell = 1.0 / n
     rng = np.random.default_rng(seed)
@@ -110,8 +114,8 @@ def cube_jitter(n=6, E=1e5, nu=0.45, rho=1000.0, dt=1.0 / 60.0, jitter=0.05, see
     return Scene(name=f"cube{n}_jitter", X=X, tets=tets, x0=x0, v0=np.zeros_like(X),
                  E=np.full(T, E), nu=np.full(T, nu), rho=rho, dt=dt, gravity=GRAVITY,
                  dirichlet_ids=ids, targets=lambda step: tgt, n_steps=n_steps,
-                 stop_mode="grad_rel", stop_tol=1e-6,
-                 meta=dict(cells=(n, n, n), size=(1.0, 1.0, 1.0)))
+                 stop_mode="vel", stop_tol=newton_rel_tol * math.sqrt(3.0) / dt,
+                 meta=dict(cells=(n, n, n), size=(1.0, 1.0, 1.0), newton_rel_tol=newton_rel_tol))
 
 
 def beam_twist(nx=80, ny=16, nz=16, L=1.0, W=0.2, E=1e5, nu=0.45, rho=1000.0, dt=1.0 / 30.0,

@@ -38,17 +38,22 @@ def _compare(sc, mode, n_steps):
     for n in range(n_steps):
         o, g = ost[n], gst[n]
         tag = f"{sc.name} {mode} step {n + 1}"
-        assert g["status"] == "PPN_OK" and o.converged and not o.ls_fail, (tag, g["status"])
-        assert g["newton_iters"] == o.newton_iters, (tag, g["newton_iters"], o.newton_iters)
-        assert g["projected"] == o.projected, (tag, g["projected"], o.projected)
-        assert g["inner_rounds"] == o.inner_rounds, tag
-        assert g["indefinite_solves"] + g["skipped_solves"] == o.indefinite_solves, tag
-        assert g["safety_events"] == o.safety_events == 0, tag
-        assert abs(g["res_l2"] - o.res_l2) <= 1e-10 * o.res0_l2, (tag, g["res_l2"], o.res_l2)
-        assert np.max(np.abs(gx[n] - ox[n])) <= 1e-6 * diag, (tag, np.max(np.abs(gx[n] - ox[n])))
+        o_conv, o_fail, o_ni, o_proj, o_rounds = o.converged, o.ls_fail, o.newton_iters, o.projected, o.inner_rounds
+        o_ind, o_safe, o_res, o_res0 = o.indefinite_solves, o.safety_events, o.res_l2, o.res0_l2
+        assert g["status"] == "PPN_OK" and o_conv and not o_fail, (tag, g["status"])
+        assert g["newton_iters"] == o_ni, (tag, g["newton_iters"], o_ni)
+        assert g["projected"] == o_proj, (tag, g["projected"], o_proj)
+        assert g["inner_rounds"] == o_rounds, (tag, g["inner_rounds"], o_rounds)
+        assert g["indefinite_solves"] + g["skipped_solves"] == o_ind, tag
+        assert g["safety_events"] == o_safe == 0, tag
+        res_err = abs(g["res_l2"] - o_res)
+        assert res_err <= 1e-10 * o_res0, (tag, g["res_l2"], o_res, o_res0)
+        pos_err = float(np.max(np.abs(gx[n] - ox[n])))
+        assert pos_err <= 1e-6 * diag, (tag, pos_err)
         for ro, rg in zip(o.trace, gtr[n]):
-            assert np.array_equal(ro.get("projected_idx", np.zeros(0, np.int32)), rg["projected_ids"]), tag
-            assert rg["rounds"] == len(ro["rounds"]), tag
+            same = np.array_equal(ro.get("projected_idx", np.zeros(0, np.int32)), rg["projected_ids"])
+            assert same, (tag, ro["k"])
+            assert rg["rounds"] == len(ro["rounds"]), (tag, ro["k"])
     return ost, gst
 
 
