@@ -30,7 +30,7 @@ from .pcg import pcg_block_jacobi
 from .project import project_to_pd
 
 
-def sample_costs(sc, n_sample=262144, n_proj=20000, pcg_iters=10):
+def sample_costs(sc, n_sample=786432, n_proj=150000, pcg_iters=60):
     stp = Stepper(sc.X, sc.tets, sc.E, sc.nu, sc.rho, sc.dt, sc.gravity, sc.dirichlet_ids,
                   Params(), x0=sc.x0, v0=sc.v0)
     stp.set_targets(sc.targets(1))
@@ -83,7 +83,7 @@ def per_step_seconds(c, counts):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--n-sample", type=int, default=262144)
+    ap.add_argument("--n-sample", type=int, default=786432)
     a = ap.parse_args()
     from scenes import config
     t = time.perf_counter()

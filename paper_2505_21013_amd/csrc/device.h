@@ -5,10 +5,11 @@
 //   vertex vectors AoS [N][3]: x, x^n, v, xhat, g, dx, r, q; PCG (z, d) records [2][N][6]
 //   vertex slots   AoS [4T][9]: corner gradient (3) + diagonal block (6)
 //   edge slots     AoS [6T][9]: off-diagonal block, row-major, global orientation
-//   BCSR values    sliced ELL: rows in groups of 64 (one wavefront), each group
-//                  padded to its longest row; per slot, the 9 entries of the 64
-//                  rows' blocks are stored entry-major (value (slot*9 + c)*64 + lane),
-//                  so every load of the matrix product is one contiguous 512-byte run
+//   BCSR values    sliced ELL: rows in groups of 64 (one wavefront), slot-major
+//                  (slot s of group g is block row s*n_groups + g); per block row
+//                  the 9 entries of the 64 rows' blocks are entry-major (value
+//                  (slot*9 + c)*64 + lane), so every load of the matrix product is
+//                  one contiguous 512-byte run
 //   block-Jacobi   SoA [9][N]: inverse of each diagonal block
 #pragma once
 #include <hip/hip_runtime.h>
@@ -48,7 +49,7 @@ struct Dev {
   int32_t rows_per_wg = 0;  // vertex chunk per workgroup of those kernels
   int32_t Gp = 0;         // workgroups of the PCG kernels (multiple of 8; 256 rows each)
   int32_t n_groups = 0;   // 64-row groups of the sliced-ELL matrix
-  int64_t n_slots = 0;
+  int64_t n_slots = 0;    // smax * n_groups (slot-major block rows)
   int32_t nD = 0;         // Dirichlet vertices
   double h = 1.0 / 30.0;
   double k_dir = 1e8;
@@ -72,7 +73,6 @@ struct Dev {
   int32_t* vslot_elem = nullptr; // [4T]
   int32_t* eptr = nullptr;       // [E+1]
   int32_t* gslots = nullptr;     // [n_groups] slots of each 64-row group
-  int32_t* goff = nullptr;       // [n_groups + 1] first slot of each group
   int32_t* col = nullptr;        // [n_slots * 64] column of each (slot, lane)
   int32_t* diag_blk = nullptr;   // [N] value base index of the diagonal block
   int32_t* eblk_up = nullptr;    // [E] value base index of block (lo, hi)

@@ -24,7 +24,8 @@
 // Matrix product: one row per lane, one 64-row sliced-ELL group per wavefront
 // (uniform slot loop; every column-index and block-entry load is one contiguous
 // 256 / 512-byte run), 4 groups per 256-thread workgroup, workgroups mapped to
-// contiguous row ranges per XCD.
+// contiguous row ranges per XCD.  Slot-major storage keeps the wavefronts that
+// walk their groups' slots at the same pace inside a narrow window of memory.
 #include <hip/hip_runtime.h>
 
 #include "k_common.h"
@@ -90,11 +91,10 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
                                                  double beta, int g, int l, double& q0, double& q1,
                                                  double& q2) {
   const int S = D.gslots[g];
-  const int base = D.goff[g];
   q0 = q1 = q2 = 0.0;
 #pragma unroll 4
   for (int s = 0; s < S; ++s) {
-    const int slot = base + s;
+    const int slot = s * D.n_groups + g;
     const int c = D.col[slot * kSell + l];
     double d0, d1, d2;
     if (kZD) {
@@ -126,18 +126,19 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const doubl
                                                        bool with_d, int g, int l, double qz[3],
                                                        double qd[3]) {
   const int S = D.gslots[g];
-  const int base = D.goff[g];
   qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = 0.0;
-#pragma unroll 4
+#pragma unroll 1
   for (int s = 0; s < S; ++s) {
-    const int slot = base + s;
+    const int slot = s * D.n_groups + g;
     const int c = D.col[slot * kSell + l];
     const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
     const double2 a = p[0], b = p[1];
     const double* v = D.vals + size_t(slot) * (9 * kSell) + l;
     double w[9];
+    // The matrix is streamed once per product and is larger than the caches:
+    // non-temporal loads keep it from evicting the gathered (z, d) records.
 #pragma unroll
-    for (int e = 0; e < 9; ++e) w[e] = v[e * kSell];
+    for (int e = 0; e < 9; ++e) w[e] = __builtin_nontemporal_load(v + e * kSell);
     qz[0] += w[0] * a.x + w[1] * a.y + w[2] * b.x;
     qz[1] += w[3] * a.x + w[4] * a.y + w[5] * b.x;
     qz[2] += w[6] * a.x + w[7] * a.y + w[8] * b.x;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, int j) {
       x[c] = D.dx[3 * i + c];
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) P[k] = D.pinv[k * N + i];
+    for (int k = 0; k < 9; ++k) P[k] = __builtin_nontemporal_load(D.pinv + k * N + i);
   }
   const double kap = reduce_partials(D.part + kPartKappa * Gp, Gp, lds);
   if (kap <= 0.0) { pcg_finish(D, 1, j + 1); return; }

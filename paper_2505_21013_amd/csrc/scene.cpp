@@ -141,7 +141,6 @@ void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* t
     D_.vslot_elem = alloc<int32_t>(4 * m);
     D_.eptr = alloc<int32_t>(size_t(D_.E) + 1);
     D_.gslots = alloc<int32_t>(size_t(D_.n_groups));
-    D_.goff = alloc<int32_t>(size_t(D_.n_groups) + 1);
     D_.col = alloc<int32_t>(size_t(D_.n_slots) * kSell);
     D_.diag_blk = alloc<int32_t>(n);
     D_.eblk_up = alloc<int32_t>(size_t(D_.E));
@@ -183,7 +182,6 @@ void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* t
     up(D_.vslot_elem, topo_.vslot_elem.data(), 4 * m * 4);
     up(D_.eptr, topo_.eptr.data(), (size_t(D_.E) + 1) * 4);
     up(D_.gslots, topo_.gslots.data(), size_t(D_.n_groups) * 4);
-    up(D_.goff, topo_.goff.data(), (size_t(D_.n_groups) + 1) * 4);
     up(D_.col, topo_.sell_col.data(), size_t(D_.n_slots) * kSell * 4);
     up(D_.diag_blk, topo_.diag_base.data(), n * 4);
     up(D_.eblk_up, topo_.eup_base.data(), size_t(D_.E) * 4);

@@ -125,14 +125,13 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
     t.eblk_lo[k] = bl;
   }
 
-  // ---- sliced-ELL layout of the same blocks
+  // ---- sliced-ELL layout of the same blocks, slot-major
   t.n_groups = (N + kSell - 1) / kSell;
   t.gslots.assign(t.n_groups, 0);
-  t.goff.assign(t.n_groups + 1, 0);
   for (int32_t i = 0; i < N; ++i)
     t.gslots[i / kSell] = std::max(t.gslots[i / kSell], t.row_ptr[i + 1] - t.row_ptr[i]);
-  for (int32_t g = 0; g < t.n_groups; ++g) t.goff[g + 1] = t.goff[g] + t.gslots[g];
-  t.n_slots = t.goff[t.n_groups];
+  t.smax = *std::max_element(t.gslots.begin(), t.gslots.end());
+  t.n_slots = int64_t(t.smax) * t.n_groups;
   if (t.n_slots * 9 * kSell >= (int64_t(1) << 31)) {
     err = "matrix too large for 32-bit sliced-ELL indices";
     return false;
@@ -142,8 +141,8 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
   for (int32_t g = 0; g < t.n_groups; ++g)
     for (int32_t l = 0; l < kSell; ++l) {
       const int32_t i = g * kSell + l;
-      for (int32_t s = 0; s < t.gslots[g]; ++s) {
-        const int64_t slot = t.goff[g] + s;
+      for (int32_t s = 0; s < t.smax; ++s) {
+        const int64_t slot = int64_t(s) * t.n_groups + g;
         int32_t c = i < N ? i : 0;
         if (i < N && s < t.row_ptr[i + 1] - t.row_ptr[i]) {
           const int32_t k = t.row_ptr[i] + s;

@@ -45,16 +45,18 @@ struct Topology {
   std::vector<int32_t> eblk_up;    // [E] block (lo, hi)
   std::vector<int32_t> eblk_lo;    // [E] block (hi, lo)
 
-  // Sliced-ELL copy of the pattern used by the device (see kSell below): rows
-  // in groups of 64, group g padded to gslots[g] = its longest row; slot s of
-  // group g starts at goff[g] + s.  Entry c of the block in slot s, row lane l
-  // lives at value index (goff[g] + s) * 9 * 64 + c * 64 + l; its column at
-  // (goff[g] + s) * 64 + l.  Padding slots hold column = the row itself and
-  // zero values.
+  // Sliced-ELL copy of the pattern used by the device: rows in groups of 64
+  // (kSell), group g using gslots[g] = its longest row.  Storage is slot-major:
+  // slot s of group g is block row (s * n_groups + g), s < smax (the longest row
+  // of the mesh), so that wavefronts walking their groups' slots in step read
+  // neighbouring memory.  Entry c of the block in (slot s, group g, lane l)
+  // lives at value index ((s * n_groups + g) * 9 + c) * 64 + l; its column at
+  // (s * n_groups + g) * 64 + l.  Slots past a row's end hold column = the row
+  // itself and zero values; slots past a group's end are never read.
   int32_t n_groups = 0;
-  int64_t n_slots = 0;              // sum of gslots (block rows of 64)
+  int32_t smax = 0;
+  int64_t n_slots = 0;              // smax * n_groups block rows of 64
   std::vector<int32_t> gslots;      // [n_groups]
-  std::vector<int32_t> goff;        // [n_groups + 1]
   std::vector<int32_t> sell_col;    // [n_slots * 64]
   std::vector<int32_t> csr_base;    // [NB] value base index of each CSR block
   std::vector<int32_t> diag_base;   // [N]

@@ -1,0 +1,42 @@
+"""The 16^3-cell compressed cube (24,576 tets) over the whole 50-step schedule
+in PN, PDN and PPN, against the oracle's record in
+tests/golden/cube16_compress_oracle.json (written by make_cube16_golden.py
+from the oracle only): per step the same Newton-iteration and projection
+counts, the final residual within 1e-10 of the step's initial residual, and
+sampled final positions within 1e-6 of the bounding-box diagonal."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2505_21013_amd import run_steps
+from scenes import cube_compress
+
+from helpers import gpu_scene
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.parametrize("mode", ["PPN", "PDN", "PN"])
+def test_cube16_schedule_matches_oracle(mode):
+    gold = json.load(open(os.path.join(HERE, "golden", "cube16_compress_oracle.json")))
+    ref = gold["modes"][mode]
+    sc = cube_compress(n=16, n_steps=50, ramp_steps=50)
+    gpu = gpu_scene(sc)
+    stats = run_steps(gpu, sc, mode, 50)
+    x = gpu.ppn_get_positions()
+    gpu.close()
+    for n, (g, o) in enumerate(zip(stats, ref["steps"])):
+        tag = (mode, n + 1)
+        # PN does not converge within 100 iterations on some steps; the GPU must agree
+        assert (g["status"] == "PPN_OK") == o["converged"], (tag, g["status"])
+        assert g["newton_iters"] == o["newton_iters"], (tag, g["newton_iters"], o["newton_iters"])
+        assert g["projected"] == o["projected"], (tag, g["projected"], o["projected"])
+        assert g["inner_rounds"] == o["inner_rounds"], tag
+        assert abs(g["res_l2"] - o["res_l2"]) <= 1e-10 * o["res0_l2"], (tag, g["res_l2"], o["res_l2"])
+    diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
+    sample = np.array(gold["sample_vertices"])
+    err = float(np.max(np.abs(x[sample] - np.array(ref["final_x_sample"]))))
+    assert err <= 1e-6 * diag, err
