@@ -11,10 +11,12 @@
 //    translation block (zero up to rounding) and the remaining 9x9 block K
 //    carries the rest of the spectrum.  The translation eigenvalues (0) are
 //    clamped to eps exactly, so Delta H = U diag(eps I_3, Delta K) U.
-//  * Cyclic-by-row Jacobi on K (36 rotations per sweep, fully unrolled with
-//    compile-time indices), eigenvectors accumulated in a 9x9 register
-//    array, stopping when off(K) <= 1e-15 |K|_F or after 15 sweeps.  Every
-//    lane of a wavefront sweeps until all 64 have converged.
+//  * Cyclic Jacobi on K in round-robin order (9 rounds of 4 disjoint
+//    rotations per sweep, fully unrolled with compile-time indices), stopping
+//    when off(K) <= 1e-15 |K|_F (FP32: ~3e-7) or after 15 sweeps.  Every lane
+//    of a wavefront sweeps until all 64 have converged.
+//  * The element matrix is streamed block by block on the way in (into K) and
+//    on the way out (H + Delta H), so only K, V and one 3x3 block are live.
 #include <hip/hip_runtime.h>
 
 #include "k_common.h"
@@ -38,126 +40,203 @@ __host__ __device__ constexpr double hs(int A, int a) {
              : -1.0;
 }
 
-// One Jacobi rotation annihilating a(P,Q) (Rutishauser's update with tau = tan(theta/2)).
-template <int P, int Q>
-__device__ __forceinline__ void jrot(double* a, double* v) {
-  const double apq = a[ui9(P, Q)];
-  const double app = a[ui9(P, P)], aqq = a[ui9(Q, Q)];
-  const double d = aqq - app;
-  const double den = fabs(d) + sqrt(d * d + 4.0 * apq * apq);
-  const double t = den > 0.0 ? (d >= 0.0 ? 2.0 * apq : -2.0 * apq) / den : 0.0;
-  const double c = 1.0 / sqrt(1.0 + t * t);
-  const double s = t * c;
-  const double tau = s / (1.0 + c);
-  a[ui9(P, P)] = app - t * apq;
-  a[ui9(Q, Q)] = aqq + t * apq;
-  a[ui9(P, Q)] = 0.0;
+// Working state of one element, held by one lane: the upper triangle of the
+// 9x9 matrix and the accumulated eigenvector matrix V (row-major).
+template <typename T>
+struct EigLane {
+  T a[45];
+  T v[81];
+};
+
+// Reciprocal and reciprocal square root from the hardware estimates refined
+// by Newton steps (the FP64 estimates carry about 23 correct bits, two steps
+// bring them to the last bit).  Arguments are positive normal numbers.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(y, fmaf(-x, y, 1.0f), y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+__device__ __forceinline__ float rsq_nr(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  return fmaf(0.5f * y, fmaf(-x * y, y, 1.0f), y);
+}
+
+// Rotation annihilating a(P,Q): t = tan(theta), s = sin(theta), tau = tan(theta/2).
+template <typename T>
+struct Rot {
+  T t, s, tau;
+};
+
+template <int P, int Q, typename T>
+__device__ __forceinline__ Rot<T> angle(const EigLane<T>& L) {
+  const T apq = L.a[ui9(P, Q)];
+  const T d = L.a[ui9(Q, Q)] - L.a[ui9(P, P)];
+  const T x = d * d + T(4) * apq * apq;
+  const bool act = x > (sizeof(T) == 8 ? T(1e-280) : T(1e-30));
+  const T r = x * rsq_nr(act ? x : T(1));  // sqrt(d^2 + 4 apq^2)
+  const T inv = rcp_nr(act ? fabs(d) + r : T(1));
+  const T t = act ? T(2) * (d >= T(0) ? apq : -apq) * inv : T(0);
+  const T c = rsq_nr(T(1) + t * t);
+  const T s = t * c;
+  return {t, s, s * rcp_nr(T(1) + c)};
+}
+
+// Applies the rotation of (P,Q) (Rutishauser's update).  Entries of other
+// disjoint pairs' 2x2 diagonal blocks are not touched, so the rotations of one
+// round commute and their angles can all be taken before any is applied.
+template <int P, int Q, typename T>
+__device__ __forceinline__ void apply(EigLane<T>& L, const Rot<T>& R) {
+  T* a = L.a;
+  const T apq = a[ui9(P, Q)];
+  a[ui9(P, P)] -= R.t * apq;
+  a[ui9(Q, Q)] += R.t * apq;
+  a[ui9(P, Q)] = T(0);
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
     if (r != P && r != Q) {
-      const double g = a[ui9(r, P)], h = a[ui9(r, Q)];
-      a[ui9(r, P)] = g - s * (h + g * tau);
-      a[ui9(r, Q)] = h + s * (g - h * tau);
+      const T g = a[ui9(r, P)], h = a[ui9(r, Q)];
+      a[ui9(r, P)] = g - R.s * (h + g * R.tau);
+      a[ui9(r, Q)] = h + R.s * (g - h * R.tau);
     }
   }
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
-    const double g = v[9 * r + P], h = v[9 * r + Q];
-    v[9 * r + P] = g - s * (h + g * tau);
-    v[9 * r + Q] = h + s * (g - h * tau);
+    const T g = L.v[9 * r + P], h = L.v[9 * r + Q];
+    L.v[9 * r + P] = g - R.s * (h + g * R.tau);
+    L.v[9 * r + Q] = h + R.s * (g - h * R.tau);
   }
 }
 
-template <int P, int Q>
+// Round-robin (parallel) ordering of the 36 pairs of 9 indices: in round k the
+// pairs {(k + i) mod 9, (k - i) mod 9}, i = 1..4, are disjoint, and each pair
+// occurs in exactly one of the 9 rounds.  The four angles of a round are
+// independent, which gives the wavefront four chains of divides and square
+// roots to overlap instead of one.
+__host__ __device__ constexpr int rr_p(int k, int i) {
+  return ((k + i) % 9) < ((k + 9 - i) % 9) ? (k + i) % 9 : (k + 9 - i) % 9;
+}
+__host__ __device__ constexpr int rr_q(int k, int i) {
+  return ((k + i) % 9) < ((k + 9 - i) % 9) ? (k + 9 - i) % 9 : (k + i) % 9;
+}
+
+template <int K>
 struct Sweep {
-  __device__ __forceinline__ static void run(double* a, double* v) {
-    jrot<P, Q>(a, v);
-    if constexpr (Q + 1 < 9) {
-      Sweep<P, Q + 1>::run(a, v);
-    } else if constexpr (P + 2 < 9) {
-      Sweep<P + 1, P + 2>::run(a, v);
-    }
+  template <typename T>
+  __device__ __forceinline__ static void run(EigLane<T>& L) {
+    const Rot<T> r1 = angle<rr_p(K, 1), rr_q(K, 1)>(L);
+    const Rot<T> r2 = angle<rr_p(K, 2), rr_q(K, 2)>(L);
+    const Rot<T> r3 = angle<rr_p(K, 3), rr_q(K, 3)>(L);
+    const Rot<T> r4 = angle<rr_p(K, 4), rr_q(K, 4)>(L);
+    apply<rr_p(K, 1), rr_q(K, 1)>(L, r1);
+    apply<rr_p(K, 2), rr_q(K, 2)>(L, r2);
+    apply<rr_p(K, 3), rr_q(K, 3)>(L, r3);
+    apply<rr_p(K, 4), rr_q(K, 4)>(L, r4);
+    if constexpr (K + 1 < 9) Sweep<K + 1>::run(L);
   }
 };
 
-// K = (U H U) restricted to the non-translational 9x9 block, from the upper
-// triangle h[78] of H.
-__device__ __forceinline__ void build_k(const double* h, double* k) {
+// Corners (a, c) of 3x3 block b of an element matrix: blocks 0..3 are the
+// diagonal blocks of the four corners, blocks 4..9 the corner pairs a < c.
+__host__ __device__ constexpr int blk_a(int b) { return b < 4 ? b : kPairA[b - 4]; }
+__host__ __device__ constexpr int blk_c(int b) { return b < 4 ? b : kPairC[b - 4]; }
+
+// Adds block b (m[3i+k] = H[3a+i][3c+k]) into the upper triangle k of
+// U H U restricted to its non-translational 9x9 part, without the factor 1/4:
+// K[(A,i)][(B,k)] = sum_{a,c} s_A(a) s_B(c) H[3a+i][3c+k], A, B = 1..3.  An
+// off-diagonal block also stands for its transpose (c, a).
+template <typename T>
+__device__ __forceinline__ void add_block_to_k(int b, const double* m, T* k) {
+  const int a = blk_a(b), c = blk_c(b);
 #pragma unroll
   for (int R = 0; R < 9; ++R) {
 #pragma unroll
     for (int C = R; C < 9; ++C) {
       const int A = 1 + R / 3, i = R % 3, B = 1 + C / 3, kk = C % 3;
-      double s = 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) s += hs(A, a) * hs(B, c) * h[ui12(3 * a + i, 3 * c + kk)];
-      k[ui9(R, C)] = 0.25 * s;
+      double t = hs(A, a) * hs(B, c) * m[3 * i + kk];
+      if (a != c) t += hs(A, c) * hs(B, a) * m[3 * kk + i];
+      k[ui9(R, C)] += T(t);
     }
   }
 }
 
-// h += Delta H where Delta H = U diag(eps I_3, dk) U.
-__device__ __forceinline__ void add_delta(double* h, const double* dk, double eps) {
+// Block b of Delta H = U diag(eps I_3, dk) U (dk: upper triangle of the 9x9 part).
+template <typename T>
+__device__ __forceinline__ void delta_block(int b, const T* dk, double eps, double* m) {
+  const int a = blk_a(b), c = blk_c(b);
 #pragma unroll
-  for (int r = 0; r < 12; ++r) {
+  for (int i = 0; i < 3; ++i) {
 #pragma unroll
-    for (int c = r; c < 12; ++c) {
-      const int a = r / 3, i = r % 3, cb = c / 3, kk = c % 3;
+    for (int kk = 0; kk < 3; ++kk) {
       double s = (i == kk) ? eps : 0.0;
 #pragma unroll
       for (int A = 1; A < 4; ++A)
 #pragma unroll
-        for (int B = 1; B < 4; ++B) s += hs(A, a) * hs(B, cb) * dk[ui9(3 * (A - 1) + i, 3 * (B - 1) + kk)];
-      h[ui12(r, c)] += 0.25 * s;
+        for (int B = 1; B < 4; ++B)
+          s += hs(A, a) * hs(B, c) * double(dk[ui9(3 * (A - 1) + i, 3 * (B - 1) + kk)]);
+      m[3 * i + kk] = 0.25 * s;
     }
   }
 }
 
-template <class IO>
-__device__ __forceinline__ void project_one(IO& io, double eps) {
-  double a[45];
-  {
-    double h[78];
-    io.load(h);
-    build_k(h, a);
+// Projection of one element.
+template <typename T, class IO>
+__device__ __forceinline__ void project_one(const IO& io, double eps) {
+  EigLane<T> L;
+#pragma unroll
+  for (int i = 0; i < 45; ++i) L.a[i] = T(0);
+#pragma unroll
+  for (int b = 0; b < 10; ++b) {
+    double m[9];
+    io.load(b, m);
+    add_block_to_k<T>(b, m, L.a);
   }
-  double v[81];
 #pragma unroll
-  for (int r = 0; r < 9; ++r)
+  for (int i = 0; i < 45; ++i) L.a[i] *= T(0.25);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) v[9 * r + c] = (r == c) ? 1.0 : 0.0;
+  for (int i = 0; i < 81; ++i) L.v[i] = (i % 10 == 0) ? T(1) : T(0);
+  const T tol2 = sizeof(T) == 8 ? T(1e-30) : T(1e-13);
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
-    double off = 0.0, dia = 0.0;
+    T off = T(0), dia = T(0);
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-      dia += a[ui9(r, r)] * a[ui9(r, r)];
+      dia += L.a[ui9(r, r)] * L.a[ui9(r, r)];
 #pragma unroll
-      for (int c = r + 1; c < 9; ++c) off += a[ui9(r, c)] * a[ui9(r, c)];
+      for (int c = r + 1; c < 9; ++c) off += L.a[ui9(r, c)] * L.a[ui9(r, c)];
     }
-    const bool done = off <= 1e-30 * (dia + 2.0 * off);
+    const bool done = off <= tol2 * (dia + T(2) * off);
     if (__all(done)) break;
-    Sweep<0, 1>::run(a, v);
+    Sweep<0>::run(L);
   }
-  // Delta K = sum_i max(eps - lambda_i, 0) q_i q_i^T
-  double w[9];
+  // Delta K = V W V^T with W = diag(max(eps - lambda_i, 0)).
+  T w[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) w[i] = fmax(eps - a[ui9(i, i)], 0.0);
+  for (int i = 0; i < 9; ++i) w[i] = fmax(T(eps) - L.a[ui9(i, i)], T(0));
 #pragma unroll
   for (int r = 0; r < 9; ++r)
 #pragma unroll
     for (int c = r; c < 9; ++c) {
-      double s = 0.0;
+      T s = T(0);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) s += w[i] * v[9 * r + i] * v[9 * c + i];
-      a[ui9(r, c)] = s;
+      for (int i = 0; i < 9; ++i) s += w[i] * L.v[9 * r + i] * L.v[9 * c + i];
+      L.a[ui9(r, c)] = s;
     }
-  {
-    double h[78];
-    io.load(h);
-    add_delta(h, a, eps);
-    io.store(h);
+#pragma unroll
+  for (int b = 0; b < 10; ++b) {
+    double m[9], d[9];
+    io.load(b, m);
+    delta_block<T>(b, L.a, eps, d);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) m[i] += d[i];
+    io.store(b, m);
   }
 }
 
@@ -180,121 +259,105 @@ struct SlotIO {
       flip[p] = v[kPairA[p]] > v[kPairC[p]];
     }
   }
-  __device__ __forceinline__ void load(double* h) const {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const double* s = D.vslots + size_t(vs[a]) * 9 + 3;
-      h[ui12(3 * a + 0, 3 * a + 0)] = s[0];
-      h[ui12(3 * a + 0, 3 * a + 1)] = s[1];
-      h[ui12(3 * a + 0, 3 * a + 2)] = s[2];
-      h[ui12(3 * a + 1, 3 * a + 1)] = s[3];
-      h[ui12(3 * a + 1, 3 * a + 2)] = s[4];
-      h[ui12(3 * a + 2, 3 * a + 2)] = s[5];
-    }
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      const int a = kPairA[p], c = kPairC[p];
+  // m[3i+k] = H[3a+i][3c+k] for block b (diagonal blocks: the slot keeps the
+  // upper triangle; edge slots keep the block of the lower-to-higher vertex).
+  __device__ __forceinline__ void load(int b, double* m) const {
+    if (b < 4) {
+      const double* s = D.vslots + size_t(vs[b]) * 9 + 3;
+      m[0] = s[0]; m[1] = s[1]; m[2] = s[2];
+      m[4] = s[3]; m[5] = s[4]; m[8] = s[5];
+      m[3] = m[1]; m[6] = m[2]; m[7] = m[5];
+    } else {
+      const int p = b - 4;
       const double* s = D.eslots + size_t(es[p]) * 9;
-      double b[9];
+      double t[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) b[k] = s[k];
+      for (int k = 0; k < 9; ++k) t[k] = s[k];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) h[ui12(3 * a + i, 3 * c + k)] = flip[p] ? b[3 * k + i] : b[3 * i + k];
+        for (int k = 0; k < 3; ++k) m[3 * i + k] = flip[p] ? t[3 * k + i] : t[3 * i + k];
     }
   }
-  __device__ __forceinline__ void store(const double* h) const {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      double* s = D.vslots + size_t(vs[a]) * 9 + 3;
-      s[0] = h[ui12(3 * a + 0, 3 * a + 0)];
-      s[1] = h[ui12(3 * a + 0, 3 * a + 1)];
-      s[2] = h[ui12(3 * a + 0, 3 * a + 2)];
-      s[3] = h[ui12(3 * a + 1, 3 * a + 1)];
-      s[4] = h[ui12(3 * a + 1, 3 * a + 2)];
-      s[5] = h[ui12(3 * a + 2, 3 * a + 2)];
-    }
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      const int a = kPairA[p], c = kPairC[p];
+  __device__ __forceinline__ void store(int b, const double* m) const {
+    if (b < 4) {
+      double* s = D.vslots + size_t(vs[b]) * 9 + 3;
+      s[0] = m[0]; s[1] = m[1]; s[2] = m[2];
+      s[3] = m[4]; s[4] = m[5]; s[5] = m[8];
+    } else {
+      const int p = b - 4;
       double* s = D.eslots + size_t(es[p]) * 9;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const double val = h[ui12(3 * a + i, 3 * c + k)];
-          if (flip[p]) s[3 * k + i] = val; else s[3 * i + k] = val;
-        }
+        for (int k = 0; k < 3; ++k) s[3 * i + k] = flip[p] ? m[3 * k + i] : m[3 * i + k];
     }
   }
 };
 
-// Row-major dense 12x12 matrix (upper triangle read, both triangles written).
+// Row-major dense 12x12 matrix (upper-triangle blocks read, both triangles written).
 struct DenseIO {
   const double* in;
   double* out;
-  __device__ __forceinline__ void load(double* h) const {
+  __device__ __forceinline__ void load(int b, double* m) const {
+    const int a = blk_a(b), c = blk_c(b);
 #pragma unroll
-    for (int r = 0; r < 12; ++r)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int c = r; c < 12; ++c) h[ui12(r, c)] = in[12 * r + c];
+      for (int k = 0; k < 3; ++k) {
+        // diagonal blocks: upper triangle only
+        const int r = 3 * a + i, q = 3 * c + k;
+        m[3 * i + k] = (a == c && i > k) ? in[12 * q + r] : in[12 * r + q];
+      }
   }
-  __device__ __forceinline__ void store(const double* h) const {
+  __device__ __forceinline__ void store(int b, const double* m) const {
+    const int a = blk_a(b), c = blk_c(b);
 #pragma unroll
-    for (int r = 0; r < 12; ++r)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int c = 0; c < 12; ++c) out[12 * r + c] = h[ui12(r, c)];
+      for (int k = 0; k < 3; ++k) {
+        out[12 * (3 * a + i) + 3 * c + k] = m[3 * i + k];
+        if (a != c) out[12 * (3 * c + k) + 3 * a + i] = m[3 * i + k];
+      }
   }
 };
 
+template <class IO>
+struct Guarded {
+  const IO& io;
+  bool live;
+  __device__ __forceinline__ void load(int b, double* m) const { io.load(b, m); }
+  __device__ __forceinline__ void store(int b, const double* m) const {
+    if (live) io.store(b, m);
+  }
+};
+
+// Lanes past the end still take part in the wavefront's sweep vote: they work
+// on the first element's data in registers and never store.
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_eig_all(Dev D, double eps) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
-  // Lanes past the end still take part in the wavefront's sweep vote; they
-  // work on element 0's data in registers and never store.
   const bool live = e < D.T;
   SlotIO io(D, live ? e : 0);
-  struct Guard {
-    SlotIO& io;
-    bool live;
-    __device__ void load(double* h) const { io.load(h); }
-    __device__ void store(const double* h) const {
-      if (live) io.store(h);
-    }
-  } g{io, live};
-  project_one(g, eps);
+  project_one<T>(Guarded<SlotIO>{io, live}, eps);
 }
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_eig_list(Dev D, int n, double eps) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  const bool live = t < n;
-  const int e = D.list[live ? t : 0];
-  SlotIO io(D, e);
-  struct Guard {
-    SlotIO& io;
-    bool live;
-    __device__ void load(double* h) const { io.load(h); }
-    __device__ void store(const double* h) const {
-      if (live) io.store(h);
-    }
-  } g{io, live};
-  project_one(g, eps);
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const bool live = k < n;
+  SlotIO io(D, D.list[live ? k : 0]);
+  project_one<T>(Guarded<SlotIO>{io, live}, eps);
 }
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_eig_dense(const double* in, double* out, int64_t n,
                                                        double eps) {
-  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const bool live = t < n;
-  const int64_t m = live ? t : 0;
-  struct Guard {
-    DenseIO io;
-    bool live;
-    __device__ void load(double* h) const { io.load(h); }
-    __device__ void store(const double* h) const {
-      if (live) io.store(h);
-    }
-  } g{DenseIO{in + 144 * m, out + 144 * m}, live};
-  project_one(g, eps);
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const bool live = k < n;
+  const int64_t m = live ? k : 0;
+  DenseIO io{in + 144 * m, out + 144 * m};
+  project_one<T>(Guarded<DenseIO>{io, live}, eps);
 }
 
 // Full 12x12 element matrices gathered from the slots (debug / parity output).
@@ -304,25 +367,27 @@ __global__ __launch_bounds__(kBlock) void k_elem_dense(Dev D, const int32_t* ids
   if (t >= n) return;
   const int e = ids ? ids[t] : t;
   SlotIO io(D, e);
-  double h[78];
-  io.load(h);
-  double* o = out + size_t(t) * 144;
-  for (int r = 0; r < 12; ++r)
-    for (int c = 0; c < 12; ++c) o[12 * r + c] = h[ui12(r, c)];
+  DenseIO o{nullptr, out + size_t(t) * 144};
+#pragma unroll
+  for (int b = 0; b < 10; ++b) {
+    double m[9];
+    io.load(b, m);
+    o.store(b, m);
+  }
 }
 
 void launch_eig_all(const Dev& D, double eps, hipStream_t st) {
-  k_eig_all<<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, eps);
+  k_eig_all<double><<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, eps);
 }
 
 void launch_eig_list(const Dev& D, int32_t n, double eps, hipStream_t st) {
   if (n <= 0) return;
-  k_eig_list<<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps);
+  k_eig_list<double><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps);
 }
 
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st) {
   if (n <= 0) return;
-  k_eig_dense<<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(H, out, n, eps);
+  k_eig_dense<double><<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(H, out, n, eps);
 }
 
 void launch_element_hessians(const Dev& D, const int32_t* ids, int32_t n, double* out,
