@@ -33,20 +33,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def spmv_bytes(N, NB):
+def spmv_bytes(N, NB, fp32=False):
     """Algorithmic bytes of one PCG matrix-product launch: every block value
-    (72 B) and column index (4 B), the row pointers, the gathered z and
-    previous direction (24 B each per vertex), and the new direction and
-    product written (24 B each per vertex)."""
+    (72 B, FP32 36 B) and column index (4 B), the row pointers, the gathered z
+    and previous direction (24 B each per vertex, FP32 12 B), and the new
+    direction and product written (24 B each per vertex, FP32 12 B)."""
+    if fp32:
+        return 40 * NB + 4 * (N + 1) + 4 * 12 * N
     return 76 * NB + 4 * (N + 1) + 4 * 24 * N
 
 
-def measured_traffic():
+def measured_traffic(fp32=False):
     """HBM bytes per matrix-product launch from the committed counter summary,
     valid only while the kernel source is the one the counters were taken on."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", "k_pcg_spmv_cube64_compress_ppn_fp64.md")
+    prof = os.path.join(ROOT, "profiles", "k_pcg_spmv_cube64_compress_ppn_%s.md" % ("mixed" if fp32 else "fp64"))
     src = os.path.join(ROOT, "paper_2505_21013_amd", "csrc", "k_pcg.hip")
     try:
         text = open(prof).read()
@@ -76,6 +78,71 @@ def cpu_baseline(cfg, per_step_counts):
             "s_per_step": sec}
 
 
+def run_form(a, precision, torch, np):
+    """Warm-up steps, reset to the initial state, then K timed steps."""
+    from paper_2505_21013_amd import PPN_FP64, PPN_MIXED, scene_from
+    from scenes import config
+    sc = config(a.config)
+    stream = torch.cuda.current_stream().cuda_stream
+    s = scene_from(sc, stream=stream, precision=PPN_MIXED if precision == "mixed" else PPN_FP64)
+    info = s.ppn_scene_info()
+    for n in range(1, a.warmup + 1):
+        s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
+        st = s.ppn_newton_step(a.mode)
+        print(f"[{precision}] warmup {n}: {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    s.ppn_set_state(sc.x0, sc.v0)
+    s.ppn_set_profiling(True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(1, a.steps + 1):
+        ts = time.perf_counter()
+        s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
+        st = s.ppn_newton_step(a.mode)
+        st["wall_ms"] = (time.perf_counter() - ts) * 1e3
+        stats.append(st)
+        print(f"[{precision}] step {n}: {st['wall_ms']:.1f} ms newton {st['newton_iters']} "
+              f"pcg {st['pcg_iters']} projected {st['projected']} {st['status']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    x = s.ppn_get_positions()
+    s.close()
+    tot = {k: sum(st[k] for st in stats) for k in
+           ("newton_iters", "pcg_iters", "solves", "projected", "ms_eig", "ms_spmv", "n_spmv",
+            "ls_backtracks", "inner_rounds", "refine_rounds")}
+    return {"elapsed": elapsed, "stats": stats, "tot": tot, "info": info, "x": x, "X": sc.X}
+
+
+def summary(R, K, info, np):
+    lat = np.array([st["wall_ms"] for st in R["stats"]])
+    tot = R["tot"]
+    return {
+        "p50_step_ms": float(np.percentile(lat, 50)),
+        "p99_step_ms": float(np.percentile(lat, 99)),
+        "eig_projections_per_s": (tot["projected"] / (tot["ms_eig"] * 1e-3)) if tot["ms_eig"] > 0 else None,
+        "per_step": {"newton_iters": tot["newton_iters"] / K, "pcg_iters": tot["pcg_iters"] / K,
+                     "solves": tot["solves"] / K, "projected": tot["projected"] / K,
+                     "proj_ratio": tot["projected"] / max(tot["newton_iters"] * info["n_tets"], 1),
+                     "ls_backtracks": tot["ls_backtracks"] / K},
+        "all_steps_converged": all(st["status"] == "PPN_OK" for st in R["stats"]),
+    }
+
+
+def roofline(R, precision, info, cfg):
+    tot = R["tot"]
+    fp32 = precision == "mixed"
+    spmv_avg_s = tot["ms_spmv"] / max(tot["n_spmv"], 1) * 1e-3
+    bytes_launch = spmv_bytes(info["n_verts"], info["n_blocks"], fp32)
+    achieved = bytes_launch / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
+    traffic = measured_traffic(fp32) if cfg == 2 else None
+    return {"kernel": "k_pcg_spmv (PCG matrix product, %s BCSR 3x3)" % ("FP32" if fp32 else "FP64"),
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_launch": bytes_launch, "avg_launch_us": spmv_avg_s * 1e6,
+            "launches": tot["n_spmv"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, help="workload index (2 = 1.57M-tet cube)")
     ap.add_argument("--mode", default="PPN", choices=["PN", "PDN", "PPN"])
+    ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
+                    help="fp64 or mixed alone, or both (FP64 headline, mixed reported beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stats-out", default=None, help="write per-step stats JSON here")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -106,85 +175,53 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 5}))
         return
 
-    from paper_2505_21013_amd import scene_from
-    from scenes import config
-
     torch.cuda.set_device(0)
-    sc = config(a.config)
-    stream = torch.cuda.current_stream().cuda_stream
-    s = scene_from(sc, stream=stream)
-    info = s.ppn_scene_info()
-
-    for n in range(1, a.warmup + 1):
-        s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
-        st = s.ppn_newton_step(a.mode)
-        print(f"warmup {n}: {st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
-    s.ppn_set_state(sc.x0, sc.v0)
-    s.ppn_set_profiling(True)
-
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for n in range(1, a.steps + 1):
-        ts = time.perf_counter()
-        s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
-        st = s.ppn_newton_step(a.mode)
-        st["wall_ms"] = (time.perf_counter() - ts) * 1e3
-        stats.append(st)
-        print(f"step {n}: {st['wall_ms']:.1f} ms newton {st['newton_iters']} pcg {st['pcg_iters']} "
-              f"projected {st['projected']} {st['status']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    K = a.steps
-    lat = np.array([st["wall_ms"] for st in stats])
-    tot = {k: sum(st[k] for st in stats) for k in
-           ("newton_iters", "pcg_iters", "solves", "projected", "ms_eig", "ms_spmv", "n_spmv",
-            "ls_backtracks", "inner_rounds")}
-    ok = all(st["status"] == "PPN_OK" for st in stats)
-    spmv_avg_s = tot["ms_spmv"] / max(tot["n_spmv"], 1) * 1e-3
-    bytes_launch = spmv_bytes(info["n_verts"], info["n_blocks"])
-    achieved = bytes_launch / spmv_avg_s / 1e9 if spmv_avg_s > 0 else 0.0
-    traffic = measured_traffic() if a.config == 2 else None
-
+    headline = "mixed" if a.precision == "mixed" else "fp64"
+    runs = {headline: run_form(a, headline, torch, np)}
+    if a.precision == "both":
+        runs["mixed"] = run_form(a, "mixed", torch, np)
+    R = runs[headline]
+    K, info, tot, stats = a.steps, R["info"], R["tot"], R["stats"]
     out = {
-        "metric": "Newton time steps/s (PPN, FP64) + 12x12 eigen-projections/s; p50/p99 step latency (1 GPU)",
-        "value": K / elapsed,
+        "metric": ("Newton time steps/s (PPN, %s) + 12x12 eigen-projections/s; p50/p99 step latency (1 GPU)"
+                   % ("FP64" if headline == "fp64" else "mixed FP32/FP64")),
+        "value": K / R["elapsed"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": a.warmup,
-        "ms_per_step": elapsed / K * 1e3,
+        "ms_per_step": R["elapsed"] / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if headline == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": (f"cube 64^3 cells -> {info['n_tets']} tets / {info['n_verts']} verts, "
                                 f"SNH E log-uniform [1e4,1e6] Pa, nu 0.48, dt 1/30 s, top pushed down "
                                 f"60% over 50 steps; steps 1..{K}; mode {a.mode}"
                                 if a.config == 2 else f"configuration {a.config}, mode {a.mode}"),
-                   "mode": a.mode, "n_tets": info["n_tets"], "n_verts": info["n_verts"],
-                   "n_blocks": info["n_blocks"], "parallelism": "single GPU"},
-        "p50_step_ms": float(np.percentile(lat, 50)),
-        "p99_step_ms": float(np.percentile(lat, 99)),
-        "eig_projections_per_s": (tot["projected"] / (tot["ms_eig"] * 1e-3)) if tot["ms_eig"] > 0 else None,
-        "per_step": {"newton_iters": tot["newton_iters"] / K, "pcg_iters": tot["pcg_iters"] / K,
-                     "solves": tot["solves"] / K, "projected": tot["projected"] / K,
-                     "proj_ratio": tot["projected"] / max(tot["newton_iters"] * info["n_tets"], 1),
-                     "ls_backtracks": tot["ls_backtracks"] / K},
-        "all_steps_converged": ok,
-        "roofline": {"kernel": "k_pcg_spmv (PCG matrix product, FP64 BCSR 3x3)", "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": spmv_avg_s * 1e6,
-                     "launches": tot["n_spmv"]},
+                   "mode": a.mode, "precision": headline, "n_tets": info["n_tets"],
+                   "n_verts": info["n_verts"], "n_blocks": info["n_blocks"],
+                   "parallelism": "single GPU"},
     }
+    out.update(summary(R, K, info, np))
+    out["roofline"] = roofline(R, headline, info, a.config)
+    if "mixed" in runs and headline == "fp64":
+        M = runs["mixed"]
+        diag = float(np.linalg.norm(M["X"].max(0) - M["X"].min(0)))
+        m = {"value": K / M["elapsed"], "unit": "steps/s", "ms_per_step": M["elapsed"] / K * 1e3,
+             "speedup_vs_fp64": (K / M["elapsed"]) / out["value"],
+             "dtype": "f32+f64"}
+        m.update(summary(M, K, info, np))
+        m["refine_rounds_per_solve"] = M["tot"]["refine_rounds"] / max(M["tot"]["solves"], 1)
+        m["max_position_diff_vs_fp64_run"] = float(np.max(np.abs(M["x"] - R["x"]))) / diag
+        m["roofline"] = roofline(M, "mixed", info, a.config)
+        out["mixed"] = m
     if a.stats_out:
         with open(a.stats_out, "w") as f:
             json.dump(stats, f)
-    s.close()
     if not a.no_cpu_baseline:
+        tot = R["tot"]
         counts = {"newton_iters": tot["newton_iters"] / K, "pcg_iters": tot["pcg_iters"] / K,
                   "projected": tot["projected"] / K,
                   "ls_trials": (tot["newton_iters"] + tot["ls_backtracks"]) / K}

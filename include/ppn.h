@@ -43,8 +43,12 @@ typedef struct ppn_scene ppn_scene; /* opaque, library-owned */
  * iterations (Sec. 2.2, Sec. 5.1).  PPN: Algorithm 1 (Sec. 4). */
 typedef enum { PPN_PN = 0, PPN_PDN = 1, PPN_PPN = 2 } ppn_mode;
 
-/* Arithmetic of the hot path.  Only PPN_FP64 is available in this version;
- * PPN_MIXED is rejected with PPN_ERR_ARG. */
+/* Arithmetic of the hot path.  PPN_FP64: everything in FP64.  PPN_MIXED:
+ * eigensolves and PCG (matrix, vectors, matrix product) in FP32 with FP32
+ * accumulation; element energies, gradients, Hessian assembly, dot products,
+ * the Newton residual, the line-search energy sum and the iterative-refinement
+ * residual of each linear solve stay FP64 (the FP32 solve is repeated on the
+ * FP64 residual until that meets pcg_rtol). */
 typedef enum { PPN_FP64 = 0, PPN_MIXED = 1 } ppn_precision;
 
 /* Newton stopping rule.  VEL (Sec. 5.1): stop once |dx|_inf / h < stop_tol
@@ -108,6 +112,9 @@ typedef struct {
   double ms_spmv;            /* summed duration of the sampled PCG matrix-product launches,
                                 measured with HIP events when profiling is on (else 0) [ms] */
   int64_t n_spmv;            /* sampled launches summed in ms_spmv */
+  int32_t refine_rounds;     /* PPN_MIXED: FP32 inner solves (each followed by an FP64
+                                residual); 0 in PPN_FP64 */
+  int32_t reserved1;
 } ppn_step_stats;
 
 /* One record per Newton iteration of the last step (when tracing is on). */

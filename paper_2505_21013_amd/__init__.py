@@ -269,9 +269,9 @@ class Scene:
         return out
 
 
-def scene_from(sc, stream=None, params=None, trace=False):
+def scene_from(sc, stream=None, params=None, trace=False, precision=PPN_FP64):
     """A Scene loaded with a ``scenes.Scene`` description (mesh, material, dt, first targets)."""
-    s = Scene(stream=stream)
+    s = Scene(stream=stream, precision=precision)
     s.ppn_load_mesh(sc.X, sc.tets, sc.x0)
     s.ppn_set_material(sc.rho, sc.E, sc.nu)
     s.ppn_set_time_step(sc.dt, sc.gravity)

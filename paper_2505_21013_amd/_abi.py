@@ -27,7 +27,8 @@ class ppn_step_stats(C.Structure):
                 ("ls_fail", C.c_int32), ("skipped_solves", C.c_int32), ("projected", C.c_int64),
                 ("res0_l2", C.c_double), ("res_l2", C.c_double), ("res_inf", C.c_double),
                 ("ms_total", C.c_double), ("ms_eig", C.c_double), ("ms_pcg", C.c_double),
-                ("ms_spmv", C.c_double), ("n_spmv", C.c_int64)]
+                ("ms_spmv", C.c_double), ("n_spmv", C.c_int64),
+                ("refine_rounds", C.c_int32), ("reserved1", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

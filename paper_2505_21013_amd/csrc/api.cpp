@@ -64,8 +64,8 @@ ppn_status ppn_scene_create(ppn_scene** out, void* hip_stream, int32_t precision
     return PPN_ERR_ARG;
   }
   *out = nullptr;
-  if (precision != PPN_FP64) {
-    g_error = "only PPN_FP64 is available";
+  if (precision != PPN_FP64 && precision != PPN_MIXED) {
+    g_error = "precision must be PPN_FP64 or PPN_MIXED";
     return PPN_ERR_ARG;
   }
   return guarded(nullptr, [&]() -> ppn_status {
@@ -78,7 +78,7 @@ ppn_status ppn_scene_create(ppn_scene** out, void* hip_stream, int32_t precision
     }
     auto* h = new ppn_scene;
     try {
-      h->impl = new ppn::Scene(st, own);
+      h->impl = new ppn::Scene(st, own, precision);
     } catch (...) {
       delete h;
       if (own) (void)hipStreamDestroy(st);

@@ -11,6 +11,9 @@
 //                  (slot*9 + c)*64 + lane), so every load of the matrix product is
 //                  one contiguous 512-byte run
 //   block-Jacobi   SoA [9][N]: inverse of each diagonal block
+//   mixed precision (only when requested): FP32 copies of the sliced-ELL
+//                  values and of the block-Jacobi inverse, three more [N][3]
+//                  vectors for the inner solve (correction, residual, H d)
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -40,6 +43,18 @@ struct PcgState {
   int32_t pad;
   double rr0;      // r0^T r0
   double rz[2];    // r_j^T z_j by iteration parity (beta of the next direction, alpha)
+};
+
+// Matrix (type M: FP64, or FP32 in the mixed-precision path) and FP64
+// vectors of one PCG solve.
+template <typename M>
+struct PcgVec {
+  const M* vals = nullptr;    // sliced-ELL values
+  const M* pinv = nullptr;    // [9][N] block-Jacobi inverse
+  double* zd = nullptr;       // [2][N][6] (z, d) records
+  double* r = nullptr;        // [N][3] residual
+  double* q = nullptr;        // [N][3] H d
+  double* x = nullptr;        // [N][3] solution
 };
 
 struct Dev {
@@ -91,6 +106,12 @@ struct Dev {
   double *r = nullptr, *q = nullptr, *xt = nullptr;
   double* zd = nullptr;    // [2][N][6]: (z, d) records by PCG iteration parity
   double* rinf = nullptr;  // [N]
+  // mixed precision (null in FP64 scenes)
+  float* vals32 = nullptr;  // [n_slots * 9 * 64]
+  float* pinv32 = nullptr;  // [9][N]
+  double* e = nullptr;      // [N][3] correction of one refinement round
+  double* ri = nullptr;     // [N][3] residual of the inner solve
+  double* qi = nullptr;     // [N][3] H d of the inner solve
   // selection
   uint8_t* proj = nullptr;  // [T]
   uint8_t* sel = nullptr;   // [T]
@@ -110,16 +131,33 @@ void launch_predict(const Dev& D, hipStream_t st);
 void launch_elem_eval(const Dev& D, hipStream_t st);
 void launch_assemble_full(const Dev& D, hipStream_t st);  // vertex + edge kernels, norm partials
 void launch_reduce(const Dev& D, int first_slot, int n_sum, int n_max, hipStream_t st);
+// The same over partials written with the PCG grid's stride (Gp).
+void launch_reduce_pcg(const Dev& D, int first_slot, int n_sum, hipStream_t st);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 void launch_select_count(const Dev& D, double delta, int fallback, hipStream_t st);
 void launch_select_write(const Dev& D, hipStream_t st);
 void launch_eig_all(const Dev& D, double eps, hipStream_t st);
 void launch_eig_list(const Dev& D, int32_t n, double eps, hipStream_t st);
+// FP32 eigensolves (mixed precision); the slots stay FP64.
+void launch_eig_all_f32(const Dev& D, double eps, hipStream_t st);
+void launch_eig_list_f32(const Dev& D, int32_t n, double eps, hipStream_t st);
 void launch_regather_list(const Dev& D, int32_t n, hipStream_t st);
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st);
-void launch_pcg_init(const Dev& D, hipStream_t st);
-void launch_pcg_iter(const Dev& D, int j, double tol2, int maxit, hipStream_t st,
-                     hipEvent_t ev_spmv_start = nullptr, hipEvent_t ev_spmv_stop = nullptr);
+// r = sign * src (FP64 source), x = 0, first preconditioned residual.
+void launch_pcg_init(const Dev& D, const PcgVec<double>& V, const double* src, double sign,
+                     hipStream_t st);
+void launch_pcg_init(const Dev& D, const PcgVec<float>& V, const double* src, double sign,
+                     hipStream_t st);
+void launch_pcg_iter(const Dev& D, const PcgVec<double>& V, int j, double tol2, int maxit,
+                     hipStream_t st, hipEvent_t ev_spmv_start = nullptr,
+                     hipEvent_t ev_spmv_stop = nullptr);
+void launch_pcg_iter(const Dev& D, const PcgVec<float>& V, int j, double tol2, int maxit,
+                     hipStream_t st, hipEvent_t ev_spmv_start = nullptr,
+                     hipEvent_t ev_spmv_stop = nullptr);
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+void launch_refine_init(const Dev& D, hipStream_t st);      // dx = 0, r = -g, |r|^2 partials
+void launch_refine_add(const Dev& D, const double* e, hipStream_t st);  // dx += e
+void launch_refine_residual(const Dev& D, hipStream_t st);  // r = -g - H dx, |r|^2 partials
 void launch_dx_stats(const Dev& D, hipStream_t st);  // |dx|_inf, g.dx -> scal[0..1]
 void launch_safety_dir(const Dev& D, hipStream_t st);
 void launch_rinf_from(const Dev& D, const double* g, hipStream_t st);  // rinf_i = max_c |g_(i,c)|

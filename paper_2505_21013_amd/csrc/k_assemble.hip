@@ -242,9 +242,8 @@ void launch_select_write(const Dev& D, hipStream_t st) {
 // ---------------------------------------------------------------- reductions and fills
 // Reduce partial slots [first, first + n_sum) as sums and the next n_max as
 // maxima into scal[0 .. n_sum + n_max).
-__global__ __launch_bounds__(kBlock) void k_reduce(Dev D, int first, int n_sum, int n_max) {
+__global__ __launch_bounds__(kBlock) void k_reduce(Dev D, int first, int n_sum, int n_max, int G) {
   __shared__ double lds[16];
-  const int G = D.G;
   for (int k = 0; k < n_sum + n_max; ++k) {
     const double* p = D.part + size_t(first + k) * G;
     double v;
@@ -262,7 +261,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Dev D, int first, int n_sum, 
 }
 
 void launch_reduce(const Dev& D, int first_slot, int n_sum, int n_max, hipStream_t st) {
-  k_reduce<<<1, kBlock, 0, st>>>(D, first_slot, n_sum, n_max);
+  k_reduce<<<1, kBlock, 0, st>>>(D, first_slot, n_sum, n_max, D.G);
+}
+
+void launch_reduce_pcg(const Dev& D, int first_slot, int n_sum, hipStream_t st) {
+  k_reduce<<<1, kBlock, 0, st>>>(D, first_slot, n_sum, 0, D.Gp);
 }
 
 __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {

@@ -385,6 +385,15 @@ void launch_eig_list(const Dev& D, int32_t n, double eps, hipStream_t st) {
   k_eig_list<double><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps);
 }
 
+void launch_eig_all_f32(const Dev& D, double eps, hipStream_t st) {
+  k_eig_all<float><<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, eps);
+}
+
+void launch_eig_list_f32(const Dev& D, int32_t n, double eps, hipStream_t st) {
+  if (n <= 0) return;
+  k_eig_list<float><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps);
+}
+
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st) {
   if (n <= 0) return;
   k_eig_dense<double><<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(H, out, n, eps);

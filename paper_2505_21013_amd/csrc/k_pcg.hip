@@ -18,6 +18,15 @@
 // zd[j&1] with three 16-byte loads per column and writes d_j into zd[(j+1)&1];
 // the update writes z_{j+1} next to it.
 //
+// The kernels are templates on the matrix type M.  FP64 is the plain path.
+// With M = FP32 (the mixed-precision path) the sliced-ELL values and the
+// block-Jacobi inverse are stored in FP32 and the matrix product is formed and
+// accumulated in FP32, which halves the bytes of the dominant stream; the CG
+// vectors, their recurrences and all dot products stay FP64, so the Krylov
+// iteration itself loses nothing to FP32 rounding.  Each such solve is refined
+// against the FP64 system (r = -g - H dx with the FP64 matrix, then another
+// solve on r) until the FP64 residual meets the tolerance.
+//
 // The product is formed as H z + beta H d_old so that the streaming loop does
 // not wait for this iteration's reductions.
 //
@@ -27,6 +36,8 @@
 // contiguous row ranges per XCD.  Slot-major storage keeps the wavefronts that
 // walk their groups' slots at the same pace inside a narrow window of memory.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "k_common.h"
 #include "topology.h"
@@ -43,9 +54,11 @@ __device__ inline void pcg_finish(const Dev& D, int ind, int iters) {
   }
 }
 
-// r = -g, x = 0, z = P^-1 r into zd[0]; partials of r^T r, r^T z and the
-// count of diagonal blocks failing Sylvester's criterion.
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D) {
+// r = sign * src, x = 0, z = P^-1 r into zd[0]; partials of r^T r, r^T z and
+// the count of diagonal blocks failing Sylvester's criterion.
+template <typename M>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, const double* src,
+                                                         double sign) {
   __shared__ double lds[16];
   const int Gp = D.Gp, N = D.N;
   const int w = logical_wg(Gp);
@@ -55,15 +68,16 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D) {
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      r[c] = -D.g[3 * i + c];
-      D.r[3 * i + c] = r[c];
-      D.dx[3 * i + c] = 0.0;
+      r[c] = sign * src[3 * i + c];
+      V.r[3 * i + c] = r[c];
+      V.x[3 * i + c] = 0.0;
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double zc = D.pinv[(3 * c) * N + i] * r[0] + D.pinv[(3 * c + 1) * N + i] * r[1] +
-                        D.pinv[(3 * c + 2) * N + i] * r[2];
-      D.zd[6 * size_t(i) + c] = zc;
+      const double zc = double(V.pinv[(3 * c) * N + i]) * r[0] +
+                        double(V.pinv[(3 * c + 1) * N + i]) * r[1] +
+                        double(V.pinv[(3 * c + 2) * N + i]) * r[2];
+      V.zd[6 * size_t(i) + c] = zc;
       rz += r[c] * zc;
       rr += r[c] * r[c];
     }
@@ -84,11 +98,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D) {
   }
 }
 
-// q_i = sum over the row's slots of B d_col.  kZD: d_col = z_col + beta dold_col
-// gathered from interleaved records; otherwise d_col is read from a plain [N][3] vector.
-template <bool kZD, bool kDir>
+// q_i = sum over the row's slots of B d_col, d read from a plain [N][3] vector (FP64).
 __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __restrict__ src,
-                                                 double beta, int g, int l, double& q0, double& q1,
+                                                 int g, int l, double& q0, double& q1,
                                                  double& q2) {
   const int S = D.gslots[g];
   q0 = q1 = q2 = 0.0;
@@ -96,23 +108,7 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
   for (int s = 0; s < S; ++s) {
     const int slot = s * D.n_groups + g;
     const int c = D.col[slot * kSell + l];
-    double d0, d1, d2;
-    if (kZD) {
-      const double2* p = reinterpret_cast<const double2*>(src + 6 * size_t(c));
-      const double2 a = p[0], b = p[1], e = p[2];
-      d0 = a.x;
-      d1 = a.y;
-      d2 = b.x;
-      if (kDir) {
-        d0 += beta * b.y;
-        d1 += beta * e.x;
-        d2 += beta * e.y;
-      }
-    } else {
-      d0 = src[3 * c];
-      d1 = src[3 * c + 1];
-      d2 = src[3 * c + 2];
-    }
+    const double d0 = src[3 * c], d1 = src[3 * c + 1], d2 = src[3 * c + 2];
     const double* v = D.vals + size_t(slot) * (9 * kSell) + l;
     q0 += v[0 * kSell] * d0 + v[1 * kSell] * d1 + v[2 * kSell] * d2;
     q1 += v[3 * kSell] * d0 + v[4 * kSell] * d1 + v[5 * kSell] * d2;
@@ -122,31 +118,36 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
 
 // Split product over the gathered (z, d_old) records: qz = H z and qd = H d_old,
 // so that q = H (z + beta d_old) = qz + beta qd needs beta only at the end.
-__device__ __forceinline__ void sell_row_product_split(const Dev& D, const double* __restrict__ zd,
-                                                       bool with_d, int g, int l, double qz[3],
-                                                       double qd[3]) {
+// The arithmetic and the accumulation are in the matrix type M (FP32 for the
+// FP32 matrix: the gathered FP64 vectors are rounded on load).
+template <typename M>
+__device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __restrict__ vals,
+                                                       const double* __restrict__ zd, bool with_d,
+                                                       int g, int l, M qz[3], M qd[3]) {
   const int S = D.gslots[g];
-  qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = 0.0;
+  qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = M(0);
 #pragma unroll 1
   for (int s = 0; s < S; ++s) {
     const int slot = s * D.n_groups + g;
     const int c = D.col[slot * kSell + l];
     const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
     const double2 a = p[0], b = p[1];
-    const double* v = D.vals + size_t(slot) * (9 * kSell) + l;
-    double w[9];
+    const M z0 = M(a.x), z1 = M(a.y), z2 = M(b.x);
+    const M* v = vals + size_t(slot) * (9 * kSell) + l;
+    M w[9];
     // The matrix is streamed once per product and is larger than the caches:
     // non-temporal loads keep it from evicting the gathered (z, d) records.
 #pragma unroll
     for (int e = 0; e < 9; ++e) w[e] = __builtin_nontemporal_load(v + e * kSell);
-    qz[0] += w[0] * a.x + w[1] * a.y + w[2] * b.x;
-    qz[1] += w[3] * a.x + w[4] * a.y + w[5] * b.x;
-    qz[2] += w[6] * a.x + w[7] * a.y + w[8] * b.x;
+    qz[0] += w[0] * z0 + w[1] * z1 + w[2] * z2;
+    qz[1] += w[3] * z0 + w[4] * z1 + w[5] * z2;
+    qz[2] += w[6] * z0 + w[7] * z1 + w[8] * z2;
     if (with_d) {
       const double2 e = p[2];
-      qd[0] += w[0] * b.y + w[1] * e.x + w[2] * e.y;
-      qd[1] += w[3] * b.y + w[4] * e.x + w[5] * e.y;
-      qd[2] += w[6] * b.y + w[7] * e.x + w[8] * e.y;
+      const M d0 = M(b.y), d1 = M(e.x), d2 = M(e.y);
+      qd[0] += w[0] * d0 + w[1] * d1 + w[2] * d2;
+      qd[1] += w[3] * d0 + w[4] * d1 + w[5] * d2;
+      qd[2] += w[6] * d0 + w[7] * d1 + w[8] * d2;
     }
   }
 }
@@ -154,13 +155,14 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const doubl
 // The streaming loop does not depend on this iteration's scalars: the partial
 // sums that decide beta and the stop test are loaded first, the product runs,
 // and only then are the partials combined (their load latency hides under the loop).
-template <bool kFirst>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, int j, double tol2, int maxit) {
+template <typename M, bool kFirst>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int j, double tol2,
+                                                        int maxit) {
   __shared__ double lds[16];
   if (D.pcg->done) return;
   const int Gp = D.Gp;
-  const double* zcur = D.zd + ((j & 1) ? 6 * size_t(D.N) : 0);
-  double* znext = D.zd + ((j & 1) ? 0 : 6 * size_t(D.N));
+  const double* zcur = V.zd + ((j & 1) ? 6 * size_t(D.N) : 0);
+  double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(D.N));
   const double* pa = D.part + kPartRR * Gp;
   const double* pb = D.part + ((j & 1) ? kPartRZ1 : kPartRZ0) * Gp;
   double sa = 0.0, sb = 0.0, sc = 0.0;
@@ -172,8 +174,8 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, int j, double tol
   const int w = logical_wg(Gp);
   const int i = w * kPcgBlock + threadIdx.x;
   const int g = i / kSell, l = i % kSell;
-  double qz[3] = {0, 0, 0}, qd[3] = {0, 0, 0};
-  if (g < D.n_groups) sell_row_product_split(D, zcur, !kFirst, g, l, qz, qd);
+  M qz[3] = {0, 0, 0}, qd[3] = {0, 0, 0};
+  if (g < D.n_groups) sell_row_product_split<M>(D, V.vals, zcur, !kFirst, g, l, qz, qd);
 
   sa = wave_sum(sa);
   sb = wave_sum(sb);
@@ -209,22 +211,22 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, int j, double tol
     const double2* p = reinterpret_cast<const double2*>(zcur + 6 * size_t(i));
     const double2 a = p[0], b = p[1], e = p[2];
     double dn0 = a.x, dn1 = a.y, dn2 = b.x;
-    double q0 = qz[0], q1 = qz[1], q2 = qz[2];
+    double q0 = double(qz[0]), q1 = double(qz[1]), q2 = double(qz[2]);
     if (!kFirst) {
       dn0 += beta * b.y;
       dn1 += beta * e.x;
       dn2 += beta * e.y;
-      q0 += beta * qd[0];
-      q1 += beta * qd[1];
-      q2 += beta * qd[2];
+      q0 += beta * double(qd[0]);
+      q1 += beta * double(qd[1]);
+      q2 += beta * double(qd[2]);
     }
     double* o = znext + 6 * size_t(i) + 3;
     o[0] = dn0;
     o[1] = dn1;
     o[2] = dn2;
-    D.q[3 * i] = q0;
-    D.q[3 * i + 1] = q1;
-    D.q[3 * i + 2] = q2;
+    V.q[3 * i] = q0;
+    V.q[3 * i + 1] = q1;
+    V.q[3 * i + 2] = q2;
     kap = dn0 * q0 + dn1 * q1 + dn2 * q2;
   }
   kap = block_sum(kap, lds);
@@ -233,11 +235,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, int j, double tol
 
 // The row's inputs are loaded before the d^T q partials are combined, so both
 // latencies overlap.
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, int j) {
+template <typename M>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, int j) {
   __shared__ double lds[16];
   if (D.pcg->done) return;
   const int Gp = D.Gp, N = D.N;
-  double* znext = D.zd + ((j & 1) ? 0 : 6 * size_t(N));
+  double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(N));
   const int w = logical_wg(Gp);
   const int i = w * kPcgBlock + threadIdx.x;
   double d[3] = {0, 0, 0}, q[3] = {0, 0, 0}, r[3] = {0, 0, 0}, x[3] = {0, 0, 0}, P[9];
@@ -245,12 +248,12 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, int j) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       d[c] = znext[6 * size_t(i) + 3 + c];
-      q[c] = D.q[3 * i + c];
-      r[c] = D.r[3 * i + c];
-      x[c] = D.dx[3 * i + c];
+      q[c] = V.q[3 * i + c];
+      r[c] = V.r[3 * i + c];
+      x[c] = V.x[3 * i + c];
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) P[k] = __builtin_nontemporal_load(D.pinv + k * N + i);
+    for (int k = 0; k < 9; ++k) P[k] = double(__builtin_nontemporal_load(V.pinv + k * N + i));
   }
   const double kap = reduce_partials(D.part + kPartKappa * Gp, Gp, lds);
   if (kap <= 0.0) { pcg_finish(D, 1, j + 1); return; }
@@ -259,9 +262,9 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, int j) {
   if (i < N) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D.dx[3 * i + c] = x[c] + alpha * d[c];
+      V.x[3 * i + c] = x[c] + alpha * d[c];
       r[c] -= alpha * q[c];
-      D.r[3 * i + c] = r[c];
+      V.r[3 * i + c] = r[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -279,29 +282,49 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, int j) {
   }
 }
 
-void launch_pcg_init(const Dev& D, hipStream_t st) {
-  k_pcg_init<<<D.Gp, kPcgBlock, 0, st>>>(D);
+template <typename T>
+static void pcg_init(const Dev& D, const PcgVec<T>& V, const double* src, double sign,
+                     hipStream_t st) {
+  k_pcg_init<T><<<D.Gp, kPcgBlock, 0, st>>>(D, V, src, sign);
 }
 
-void launch_pcg_iter(const Dev& D, int j, double tol2, int maxit, hipStream_t st,
-                     hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
+template <typename T>
+static void pcg_iter(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
+                     hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
   if (ev_spmv_start) (void)hipEventRecord(ev_spmv_start, st);
   if (j == 0)
-    k_pcg_spmv<true><<<D.Gp, kPcgBlock, 0, st>>>(D, j, tol2, maxit);
+    k_pcg_spmv<T, true><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
   else
-    k_pcg_spmv<false><<<D.Gp, kPcgBlock, 0, st>>>(D, j, tol2, maxit);
+    k_pcg_spmv<T, false><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
   if (ev_spmv_stop) (void)hipEventRecord(ev_spmv_stop, st);
-  k_pcg_update<<<D.Gp, kPcgBlock, 0, st>>>(D, j);
+  k_pcg_update<T><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
 }
 
-// Plain q = H d (parity tests and benchmarks).
+void launch_pcg_init(const Dev& D, const PcgVec<double>& V, const double* src, double sign,
+                     hipStream_t st) {
+  pcg_init(D, V, src, sign, st);
+}
+void launch_pcg_init(const Dev& D, const PcgVec<float>& V, const double* src, double sign,
+                     hipStream_t st) {
+  pcg_init(D, V, src, sign, st);
+}
+void launch_pcg_iter(const Dev& D, const PcgVec<double>& V, int j, double tol2, int maxit,
+                     hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
+  pcg_iter(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
+}
+void launch_pcg_iter(const Dev& D, const PcgVec<float>& V, int j, double tol2, int maxit,
+                     hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
+  pcg_iter(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
+}
+
+// Plain q = H d in FP64 (parity tests and benchmarks).
 __global__ __launch_bounds__(kPcgBlock) void k_spmv_plain(Dev D, const double* d, double* q) {
   const int w = logical_wg(D.Gp);
   const int i = w * kPcgBlock + threadIdx.x;
   const int g = i / kSell, l = i % kSell;
   if (g >= D.n_groups) return;
   double q0, q1, q2;
-  sell_row_product<false, false>(D, d, 0.0, g, l, q0, q1, q2);
+  sell_row_product(D, d, g, l, q0, q1, q2);
   if (i < D.N) {
     q[3 * i] = q0;
     q[3 * i + 1] = q1;
@@ -311,6 +334,79 @@ __global__ __launch_bounds__(kPcgBlock) void k_spmv_plain(Dev D, const double* d
 
 void launch_spmv_plain(const Dev& D, const double* d, double* q, hipStream_t st) {
   k_spmv_plain<<<D.Gp, kPcgBlock, 0, st>>>(D, d, q);
+}
+
+// ---- mixed precision: FP32 inner solves refined against the FP64 system ----
+
+// dst = float(src) over n values.
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ src,
+                                                   float* __restrict__ dst, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += stride)
+    dst[k] = float(__builtin_nontemporal_load(src + k));
+}
+
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+  k_to_f32<<<unsigned(blocks), kBlock, 0, st>>>(src, dst, n);
+}
+
+// Outer start: dx = 0, r = -g, partials of |r|^2 in kPartA.
+__global__ __launch_bounds__(kPcgBlock) void k_refine_init(Dev D) {
+  __shared__ double lds[16];
+  const int w = logical_wg(D.Gp);
+  const int i = w * kPcgBlock + threadIdx.x;
+  double rr = 0.0;
+  if (i < D.N) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double rc = -D.g[3 * i + c];
+      D.r[3 * i + c] = rc;
+      D.dx[3 * i + c] = 0.0;
+      rr += rc * rc;
+    }
+  }
+  rr = block_sum(rr, lds);
+  if (threadIdx.x == 0) D.part[kPartA * D.Gp + w] = rr;
+}
+
+// dx += e (the correction of the last inner solve).
+__global__ __launch_bounds__(kPcgBlock) void k_refine_add(Dev D, const double* e) {
+  const int i = blockIdx.x * kPcgBlock + threadIdx.x;
+  if (i < 3 * D.N) D.dx[i] += e[i];
+}
+
+// r = -g - H dx in FP64, partials of |r|^2 in kPartA.
+__global__ __launch_bounds__(kPcgBlock) void k_refine_residual(Dev D) {
+  __shared__ double lds[16];
+  const int w = logical_wg(D.Gp);
+  const int i = w * kPcgBlock + threadIdx.x;
+  const int g = i / kSell, l = i % kSell;
+  double rr = 0.0;
+  if (g < D.n_groups) {
+    double q0, q1, q2;
+    sell_row_product(D, D.dx, g, l, q0, q1, q2);
+    if (i < D.N) {
+      const double r0 = -D.g[3 * i] - q0, r1 = -D.g[3 * i + 1] - q1, r2 = -D.g[3 * i + 2] - q2;
+      D.r[3 * i] = r0;
+      D.r[3 * i + 1] = r1;
+      D.r[3 * i + 2] = r2;
+      rr = r0 * r0 + r1 * r1 + r2 * r2;
+    }
+  }
+  rr = block_sum(rr, lds);
+  if (threadIdx.x == 0) D.part[kPartA * D.Gp + w] = rr;
+}
+
+void launch_refine_init(const Dev& D, hipStream_t st) {
+  k_refine_init<<<D.Gp, kPcgBlock, 0, st>>>(D);
+}
+void launch_refine_add(const Dev& D, const double* e, hipStream_t st) {
+  k_refine_add<<<(3 * D.N + kPcgBlock - 1) / kPcgBlock, kPcgBlock, 0, st>>>(D, e);
+}
+void launch_refine_residual(const Dev& D, hipStream_t st) {
+  k_refine_residual<<<D.Gp, kPcgBlock, 0, st>>>(D);
 }
 
 }  // namespace ppn

@@ -44,7 +44,8 @@ void params_defaults(ppn_params* p) {
   p->k_dirichlet = 1e8;
 }
 
-Scene::Scene(hipStream_t stream, bool own) : st_(stream), own_stream_(own) {
+Scene::Scene(hipStream_t stream, bool own, int precision)
+    : st_(stream), own_stream_(own), precision_(precision) {
   params_defaults(&prm_);
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hscal_), 64 * sizeof(double)));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hpcg_), 4 * sizeof(PcgState)));
@@ -156,6 +157,13 @@ void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* t
     for (double** p : vecs) *p = alloc<double>(3 * n);
     D_.zd = alloc<double>(12 * n);
     D_.rinf = alloc<double>(n);
+    if (precision_ == PPN_MIXED) {
+      D_.vals32 = alloc<float>(size_t(D_.n_slots) * 9 * kSell);
+      D_.pinv32 = alloc<float>(9 * n);
+      D_.e = alloc<double>(3 * n);
+      D_.ri = alloc<double>(3 * n);
+      D_.qi = alloc<double>(3 * n);
+    }
     D_.proj = alloc<uint8_t>(m);
     D_.sel = alloc<uint8_t>(m);
     D_.list = alloc<int32_t>(m);
@@ -309,9 +317,23 @@ void Scene::evaluate_at_current_x() {
   all_projected_ = false;
 }
 
+void Scene::eig_all() {
+  if (precision_ == PPN_MIXED)
+    launch_eig_all_f32(D_, prm_.eps_clamp, st_);
+  else
+    launch_eig_all(D_, prm_.eps_clamp, st_);
+}
+
+void Scene::eig_list(int32_t n) {
+  if (precision_ == PPN_MIXED)
+    launch_eig_list_f32(D_, n, prm_.eps_clamp, st_);
+  else
+    launch_eig_list(D_, n, prm_.eps_clamp, st_);
+}
+
 void Scene::project_all() {
   HIPCHK(hipEventRecord(ev_[2], st_));
-  launch_eig_all(D_, prm_.eps_clamp, st_);
+  eig_all();
   hipEvent_t stop = ev_[3];
   HIPCHK(hipEventRecord(stop, st_));
   launch_fill_u8(D_.proj, 1, D_.T, st_);
@@ -335,7 +357,7 @@ int32_t Scene::select_and_project(double delta, bool fallback) {
   if (n <= 0) return 0;
   launch_select_write(D_, st_);
   HIPCHK(hipEventRecord(ev_[2], st_));
-  launch_eig_list(D_, n, prm_.eps_clamp, st_);
+  eig_list(n);
   hipEvent_t stop = ev_[3];
   HIPCHK(hipEventRecord(stop, st_));
   if (int64_t(n) * 8 > D_.T)
@@ -361,18 +383,18 @@ void Scene::project_mask(const uint8_t* mask) {
   HIPCHK(hipMemcpyAsync(D_.proj, mask, size_t(D_.T), hipMemcpyHostToDevice, st_));
   if (ids.empty()) return;
   HIPCHK(hipMemcpyAsync(D_.list, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, st_));
-  launch_eig_list(D_, int32_t(ids.size()), prm_.eps_clamp, st_);
+  eig_list(int32_t(ids.size()));
   launch_regather_list(D_, int32_t(ids.size()), st_);
   LAUNCHCHK();
   sync();
 }
 
-void Scene::solve(int32_t& ind, int32_t& iters) {
-  const auto t0 = std::chrono::steady_clock::now();
-  launch_pcg_init(D_, st_);
+template <typename T>
+void Scene::run_pcg(const PcgVec<T>& V, const double* src, double sign, double rtol, int maxit,
+                    int32_t& ind, int32_t& iters) {
+  launch_pcg_init(D_, V, src, sign, st_);
   LAUNCHCHK();
-  const double tol2 = prm_.pcg_rtol * prm_.pcg_rtol;
-  const int maxit = prm_.pcg_maxit;
+  const double tol2 = rtol * rtol;
   // Iterations are enqueued in chunks; the status of chunk c-1 is read while
   // chunk c runs, so launches past convergence (which return at once) are at
   // most two chunks.
@@ -388,10 +410,10 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
       }
     for (; j < jend; ++j) {
       if (profile_on && j % kProfileEvery == 0)
-        launch_pcg_iter(D_, j, tol2, maxit, st_, prof_ev_[2 * (j / kProfileEvery)],
+        launch_pcg_iter(D_, V, j, tol2, maxit, st_, prof_ev_[2 * (j / kProfileEvery)],
                         prof_ev_[2 * (j / kProfileEvery) + 1]);
       else
-        launch_pcg_iter(D_, j, tol2, maxit, st_);
+        launch_pcg_iter(D_, V, j, tol2, maxit, st_);
     }
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(&hpcg_[slot], D_.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, st_));
@@ -421,8 +443,73 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
       last_stats.n_spmv++;
     }
   }
+}
+
+void Scene::solve(int32_t& ind, int32_t& iters) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (precision_ == PPN_MIXED) {
+    solve_mixed(ind, iters);
+  } else {
+    PcgVec<double> V;
+    V.vals = D_.vals;
+    V.pinv = D_.pinv;
+    V.zd = D_.zd;
+    V.r = D_.r;
+    V.q = D_.q;
+    V.x = D_.dx;
+    run_pcg(V, D_.g, -1.0, prm_.pcg_rtol, prm_.pcg_maxit, ind, iters);
+  }
   last_stats.ms_pcg +=
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Mixed precision: PCG with the FP32 rounding of H (FP32 matrix product, FP64
+// vectors), refined against the FP64 system.  Round k solves H e = r_k (zero
+// start, curvature exit as in the FP64 solve), adds e to dx and forms
+// r_{k+1} = -g - H dx with the FP64 matrix; the solve ends once |r|_2 <= rtol |g|_2, the same
+// criterion as the FP64 solve's, now on the true FP64 residual.  A round's
+// own tolerance asks for the remaining reduction (at most rtol, at least
+// kMinInner).  Iterations over all rounds count against pcg_maxit.
+void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
+  constexpr int kMaxRounds = 8;
+  constexpr double kMinInner = 1e-6;
+  launch_to_f32(D_.vals, D_.vals32, int64_t(D_.n_slots) * 9 * kSell, st_);
+  launch_to_f32(D_.pinv, D_.pinv32, int64_t(9) * D_.N, st_);
+  launch_refine_init(D_, st_);
+  launch_reduce_pcg(D_, kPartA, 1, st_);
+  LAUNCHCHK();
+  read_scal(1, hscal_);
+  const double rr0 = hscal_[0];
+  PcgVec<float> V;
+  V.vals = D_.vals32;
+  V.pinv = D_.pinv32;
+  V.zd = D_.zd;
+  V.r = D_.ri;  // D_.r holds the refinement residual, the inner solve's right-hand side
+  V.q = D_.qi;
+  V.x = D_.e;
+  ind = 0;
+  iters = 0;
+  if (rr0 == 0.0) return;
+  const double goal2 = prm_.pcg_rtol * prm_.pcg_rtol * rr0;
+  double rr = rr0;
+  for (int round = 0; round < kMaxRounds && iters < prm_.pcg_maxit; ++round) {
+    const double rtol_in = std::max(kMinInner, std::min(prm_.pcg_rtol, std::sqrt(goal2 / rr)));
+    int32_t ind_k = 0, it_k = 0;
+    run_pcg(V, D_.r, 1.0, rtol_in, prm_.pcg_maxit - iters, ind_k, it_k);
+    iters += it_k;
+    last_stats.refine_rounds++;
+    if (ind_k) {
+      ind = 1;
+      return;
+    }
+    launch_refine_add(D_, D_.e, st_);
+    launch_refine_residual(D_, st_);
+    launch_reduce_pcg(D_, kPartA, 1, st_);
+    LAUNCHCHK();
+    read_scal(1, hscal_);
+    rr = hscal_[0];
+    if (rr <= goal2) return;
+  }
 }
 
 // ---------------------------------------------------------------- one time step

@@ -19,7 +19,7 @@ struct HipError {
 
 class Scene {
  public:
-  Scene(hipStream_t stream, bool own_stream);
+  Scene(hipStream_t stream, bool own_stream, int precision);
   ~Scene();
 
   void load_mesh(int32_t n_verts, const double* rest, int32_t n_tets, const int32_t* tets,
@@ -72,10 +72,19 @@ class Scene {
   void project_all();
   int32_t select_and_project(double delta, bool fallback);
   void solve(int32_t& ind, int32_t& iters);
+  // One PCG run of the given arithmetic on the system whose right-hand side is
+  // sign * src; returns its indefiniteness flag and iteration count.
+  template <typename T>
+  void run_pcg(const PcgVec<T>& V, const double* src, double sign, double rtol, int maxit,
+               int32_t& ind, int32_t& iters);
+  void solve_mixed(int32_t& ind, int32_t& iters);
+  void eig_all();
+  void eig_list(int32_t n);
   void read_scal(int n, double* out);
 
   hipStream_t st_;
   bool own_stream_;
+  int precision_;
   Dev D_;
   Topology topo_;
   std::vector<void*> allocs_;

@@ -14,9 +14,9 @@ def oracle_stepper(sc, step=1, **params):
     return s
 
 
-def gpu_scene(sc, step=1, trace=False, **params):
+def gpu_scene(sc, step=1, trace=False, precision=0, **params):
     from paper_2505_21013_amd import scene_from
-    s = scene_from(sc, params=params or None, trace=trace)
+    s = scene_from(sc, params=params or None, trace=trace, precision=precision)
     s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(step))
     return s
 

@@ -35,7 +35,7 @@ def test_struct_layouts_match_header():
     from paper_2505_21013_amd import _abi
     # ppn_params: 5 doubles, 4 int32, 2 doubles, 2 int32, 1 double = 88 bytes
     assert ctypes.sizeof(_abi.ppn_params) == 5 * 8 + 4 * 4 + 2 * 8 + 2 * 4 + 8
-    assert ctypes.sizeof(_abi.ppn_step_stats) == 10 * 4 + 8 + 7 * 8 + 8
+    assert ctypes.sizeof(_abi.ppn_step_stats) == 10 * 4 + 8 + 7 * 8 + 8 + 2 * 4
     assert ctypes.sizeof(_abi.ppn_iter_record) == 6 * 4 + 6 * 8
 
 
@@ -50,7 +50,7 @@ def test_host_side_errors_without_gpu():
     from paper_2505_21013_amd import _abi
     lib = _abi.lib()
     h = ctypes.c_void_p()
-    assert lib.ppn_scene_create(ctypes.byref(h), None, 1) == -1  # MIXED rejected before touching HIP
-    assert b"FP64" in lib.ppn_last_error(None)
+    assert lib.ppn_scene_create(ctypes.byref(h), None, 7) == -1  # unknown precision, before touching HIP
+    assert b"PPN_MIXED" in lib.ppn_last_error(None)
     assert lib.ppn_newton_step(None, 2, None) == -1
     assert lib.ppn_project_batch_dev(None, None, 4, 1e-8, None) == -1

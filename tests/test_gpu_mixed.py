@@ -1,0 +1,193 @@
+"""Mixed precision (PPN_MIXED) against the FP64 oracle.
+
+In this form the eigensolves and the PCG iterations run in FP32 while the
+gradient, the energies, the assembly and each solve's refinement residual stay
+FP64.  The bar, per result:
+  * element projections within 2e-5 of the element matrix's magnitude (FP32
+    Jacobi), still positive semidefinite to that level;
+  * every linear solve meets the FP64 bound |H dx + g| <= rtol |g| on the
+    oracle's own operator (the refinement guarantees it);
+  * whole time steps: positions within 1e-6 of the bounding-box diagonal of
+    the oracle's trajectory; the Newton residual the step reports (FP64) within
+    1e-8 of the oracle's residual at the same state, both relative to the
+    step's initial residual (a converged residual is a sum of large cancelling
+    terms, so relative to itself it carries the FP64 rounding of those terms
+    amplified by their ratio to it); the projected-set mismatch
+    rate against the oracle, and the difference of the two trajectories' final
+    residuals (relative to the step's initial residual), printed and bounded.
+    The trajectories' final residuals are not held to 1e-8: both runs stop on
+    |dx|_inf after inexact solves (|r| <= 1e-4 |g|) whose Krylov iterates differ
+    once the arithmetic differs, so the last iterate of a step differs at the
+    level of the stopping tolerance.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.assemble import diagonal_blocks
+from oracle.fem import predictor
+from oracle.pcg import pcg_block_jacobi
+from oracle.project import project_to_pd
+from paper_2505_21013_amd import PPN_MIXED, run_steps
+from scenes import config, cube_compress
+
+from helpers import gpu_scene, oracle_stepper, squashed_state
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+SCENES = {
+    "cube6_jitter": lambda: config(0),
+    "cube4_compress": lambda: cube_compress(n=4, n_steps=4, ramp_steps=4),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(SCENES))
+def case(request):
+    sc = SCENES[request.param]()
+    orc = oracle_stepper(sc)
+    gpu = gpu_scene(sc, precision=PPN_MIXED)
+    x = squashed_state(sc, seed=sorted(SCENES).index(request.param))
+    g, ge, He, H = orc.evaluate(x)
+    yield dict(sc=sc, orc=orc, gpu=gpu, x=x, g=g, He=He)
+    gpu.close()
+
+
+def test_mixed_gradient_is_fp64(case):
+    g_gpu = case["gpu"].ppn_eval_gradient(case["x"])
+    assert np.max(np.abs(g_gpu - case["g"])) <= 1e-12 * np.max(np.abs(case["g"]))
+
+
+def test_mixed_projection(case):
+    T = case["sc"].n_tets
+    He = case["He"]
+    nrm = np.abs(He).max(axis=(1, 2))
+    Hp_gpu = case["gpu"].ppn_eval_element_hessians(case["x"], proj_mask=np.ones(T, np.uint8))
+    err = np.abs(Hp_gpu - project_to_pd(He, 1e-8)).max(axis=(1, 2))
+    assert np.all(err <= 2e-5 * nrm), (err / nrm).max()
+    lg = np.linalg.eigvalsh(0.5 * (Hp_gpu + np.swapaxes(Hp_gpu, 1, 2)))
+    assert np.all(lg[:, 0] >= -2e-5 * nrm)
+
+
+@pytest.mark.parametrize("projected", [False, True])
+def test_mixed_solve_meets_fp64_residual(case, projected):
+    T = case["sc"].n_tets
+    mask = np.ones(T, np.uint8) if projected else None
+    dx, ind, it = case["gpu"].ppn_solve(case["x"], proj_mask=mask)
+    He = case["He"].copy()
+    if projected:
+        He = project_to_pd(He, 1e-8)
+    Ho = case["orc"].asm.hessian(He, case["orc"]._diag())
+    g = case["g"]
+    _, indo, _ = pcg_block_jacobi(Ho, -g, diagonal_blocks(Ho))
+    assert ind == indo
+    if projected:
+        assert not ind
+    if not ind:
+        # Ho holds the projected element matrices in FP64; the solve's FP32
+        # projections differ from them by the projection tolerance above.
+        slack = 1e-6 if not projected else 1e-3
+        assert np.linalg.norm(Ho @ dx + g) <= 1e-4 * np.linalg.norm(g) * (1 + slack)
+        assert g @ dx < 0
+
+
+def _mask_mismatch(o_trace, g_trace):
+    """Summed symmetric difference over summed union of the per-iteration
+    projected sets, over the iterations both runs carried out."""
+    diff = union = 0
+    for ro, rg in zip(o_trace, g_trace):
+        a = set(np.asarray(ro.get("projected_idx", np.zeros(0, np.int32))).tolist())
+        b = set(np.asarray(rg["projected_ids"]).tolist())
+        diff += len(a ^ b)
+        union += len(a | b)
+    return diff, union
+
+
+@pytest.mark.parametrize("mode", ["PN", "PDN", "PPN"])
+def test_mixed_cube6_jitter_20_steps(mode):
+    sc = config(0)
+    orc_x = []
+    _, ost = oracle.run_scene(sc, mode, n_steps=sc.n_steps, trace=True,
+                              callback=lambda n, s, st: orc_x.append(s.x.copy()))
+    gpu = gpu_scene(sc, trace=True, precision=PPN_MIXED)
+    gstate, gtr = [(sc.x0.copy(), sc.v0.copy())], []
+
+    def cb(n, s, st):
+        gstate.append(s.ppn_get_state())
+        gtr.append(s.ppn_trace())
+    gst = run_steps(gpu, sc, mode, sc.n_steps, callback=cb)
+    gpu.close()
+    diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
+    diff = union = 0
+    worst_pos = worst_res = worst_traj = 0.0
+    for n in range(sc.n_steps):
+        o, g = ost[n], gst[n]
+        tag = f"{mode} step {n + 1}"
+        assert g["status"] == "PPN_OK" and o.converged, (tag, g["status"])
+        assert g["refine_rounds"] >= g["solves"], tag
+        x, _ = gstate[n + 1]
+        worst_pos = max(worst_pos, float(np.max(np.abs(x - orc_x[n]))) / diag)
+        # the oracle's residual at the state the GPU step ended in
+        st = oracle_stepper(sc, step=n + 1)
+        xp, vp = gstate[n]
+        st.xhat = predictor(xp, vp, st.h, st.gravity)
+        res = float(np.linalg.norm(st.gradient(x)))
+        worst_res = max(worst_res, abs(g["res_l2"] - res) / g["res0_l2"])
+        worst_traj = max(worst_traj, abs(g["res_l2"] - o.res_l2) / o.res0_l2)
+        d, u = _mask_mismatch(o.trace, gtr[n])
+        diff += d
+        union += u
+    rate = diff / max(union, 1)
+    print(f"\nmixed {mode}: max position error {worst_pos:.2e} diag, reported residual vs oracle "
+          f"{worst_res:.2e} res0, trajectory residual difference {worst_traj:.2e} res0, projected-set "
+          f"mismatch {rate:.4f} ({diff}/{union})")
+    assert worst_pos <= 1e-6, worst_pos
+    assert worst_res <= 1e-8, worst_res
+    assert worst_traj <= 1e-6, worst_traj
+    assert rate <= 0.05, rate
+
+
+def test_mixed_cube16_schedule_against_oracle_record():
+    gold = json.load(open(os.path.join(HERE, "golden", "cube16_compress_oracle.json")))
+    ref = gold["modes"]["PPN"]
+    sc = cube_compress(n=16, n_steps=50, ramp_steps=50)
+    gpu = gpu_scene(sc, precision=PPN_MIXED)
+    stats = run_steps(gpu, sc, "PPN", 50)
+    x = gpu.ppn_get_positions()
+    gpu.close()
+    worst_traj = 0.0
+    for n, (g, o) in enumerate(zip(stats, ref["steps"])):
+        assert (g["status"] == "PPN_OK") == o["converged"], (n + 1, g["status"])
+        worst_traj = max(worst_traj, abs(g["res_l2"] - o["res_l2"]) / o["res0_l2"])
+    diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
+    sample = np.array(gold["sample_vertices"])
+    err = float(np.max(np.abs(x[sample] - np.array(ref["final_x_sample"])))) / diag
+    print(f"\nmixed cube16 PPN: trajectory residual difference {worst_traj:.2e} res0, final "
+          f"position error {err:.2e} diag")
+    assert worst_traj <= 1e-6, worst_traj
+    assert err <= 1e-6, err
+
+
+def test_mixed_cube64_solve_and_steps():
+    sc = config(2)
+    gpu = gpu_scene(sc, precision=PPN_MIXED)
+    stats = run_steps(gpu, sc, "PPN", 2)
+    assert all(s["status"] == "PPN_OK" for s in stats)
+    x, v = gpu.ppn_get_state()
+    orc = oracle_stepper(sc, step=3)
+    orc.x, orc.v = x.copy(), v.copy()
+    orc.xhat = orc.x + sc.dt * orc.v + sc.dt ** 2 * np.asarray(sc.gravity)[None]
+    gpu.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(3))
+    xt = x + 1e-4 * np.random.default_rng(3).standard_normal(x.shape)
+    g = orc.gradient(xt)
+    g_gpu = gpu.ppn_eval_gradient(xt)
+    assert np.max(np.abs(g_gpu - g)) <= 1e-12 * np.max(np.abs(g))
+    dx, ind, it = gpu.ppn_solve(xt)
+    if not ind:
+        Hdx = orc.hessian_rows_product(xt, dx, np.arange(sc.n_verts)).reshape(-1)
+        assert np.linalg.norm(Hdx + g) <= 1e-4 * np.linalg.norm(g) * (1 + 1e-6)
+        assert g @ dx < 0
+    gpu.close()
