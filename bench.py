@@ -35,12 +35,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 def spmv_bytes(N, NB, fp32=False):
     """Algorithmic bytes of one PCG matrix-product launch: every block value
-    (72 B, FP32 36 B) and column index (4 B), the row pointers, the gathered z
-    and previous direction (24 B each per vertex, FP32 12 B), and the new
-    direction and product written (24 B each per vertex, FP32 12 B)."""
-    if fp32:
-        return 40 * NB + 4 * (N + 1) + 4 * 12 * N
-    return 76 * NB + 4 * (N + 1) + 4 * 24 * N
+    (72 B; 36 B for the FP32 matrix of the mixed form) and column index (4 B),
+    the row pointers, the gathered z and previous direction (24 B each per
+    vertex), and the new direction and product written (24 B each per vertex;
+    the vectors are FP64 in both forms)."""
+    return (40 if fp32 else 76) * NB + 4 * (N + 1) + 4 * 24 * N
 
 
 def measured_traffic(fp32=False):

@@ -107,7 +107,8 @@ struct Dev {
   double* zd = nullptr;    // [2][N][6]: (z, d) records by PCG iteration parity
   double* rinf = nullptr;  // [N]
   // mixed precision (null in FP64 scenes)
-  float* vals32 = nullptr;  // [n_slots * 9 * 64]
+  float* vals32 = nullptr;  // [n_slots * 9 * 64]: per slot four [64] float2 entry pairs
+                            // (0,1) (2,3) (4,5) (6,7), then entry 8 as [64] float
   float* pinv32 = nullptr;  // [9][N]
   double* e = nullptr;      // [N][3] correction of one refinement round
   double* ri = nullptr;     // [N][3] residual of the inner solve
@@ -155,6 +156,8 @@ void launch_pcg_iter(const Dev& D, const PcgVec<float>& V, int j, double tol2, i
                      hipStream_t st, hipEvent_t ev_spmv_start = nullptr,
                      hipEvent_t ev_spmv_stop = nullptr);
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+// FP32 copy of the sliced-ELL values, entries paired for 8-byte loads.
+void launch_sell_to_f32(const double* src, float* dst, int64_t n_slots, hipStream_t st);
 void launch_refine_init(const Dev& D, hipStream_t st);      // dx = 0, r = -g, |r|^2 partials
 void launch_refine_add(const Dev& D, const double* e, hipStream_t st);  // dx += e
 void launch_refine_residual(const Dev& D, hipStream_t st);  // r = -g - H dx, |r|^2 partials

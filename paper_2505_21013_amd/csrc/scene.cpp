@@ -473,7 +473,7 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
 void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
   constexpr int kMaxRounds = 8;
   constexpr double kMinInner = 1e-6;
-  launch_to_f32(D_.vals, D_.vals32, int64_t(D_.n_slots) * 9 * kSell, st_);
+  launch_sell_to_f32(D_.vals, D_.vals32, int64_t(D_.n_slots), st_);
   launch_to_f32(D_.pinv, D_.pinv32, int64_t(9) * D_.N, st_);
   launch_refine_init(D_, st_);
   launch_reduce_pcg(D_, kPartA, 1, st_);
