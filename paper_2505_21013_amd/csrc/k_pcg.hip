@@ -157,7 +157,9 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
                                                        int g, int l, M qz[3], M qd[3]) {
   const int S = D.gslots[g];
   qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = M(0);
-#pragma unroll 1
+  // FP64 streams from HBM and runs best with one slot in flight per lane; the
+  // cache-resident FP32 matrix gains from two (measured on the 1.57M-tet cube).
+#pragma unroll(sizeof(M) == 4 ? 2 : 1)
   for (int s = 0; s < S; ++s) {
     const int slot = s * D.n_groups + g;
     const int c = D.col[slot * kSell + l];
@@ -261,37 +263,49 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int 
 }
 
 // The row's inputs are loaded before the d^T q partials are combined, so both
-// latencies overlap.
+// latencies overlap.  The workgroup's 256 vertices own a contiguous run of
+// 768 values of each [N][3] vector: q, r and x are moved between HBM and LDS
+// with unit-stride loads and stores and read per vertex from LDS, instead of
+// three 24-byte-strided accesses per vector and lane.
 template <typename M>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, int j) {
   __shared__ double lds[16];
+  __shared__ double sq[3 * kPcgBlock], sr[3 * kPcgBlock], sx[3 * kPcgBlock];
   if (D.pcg->done) return;
   const int Gp = D.Gp, N = D.N;
   double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(N));
   const int w = logical_wg(Gp);
-  const int i = w * kPcgBlock + threadIdx.x;
-  double d[3] = {0, 0, 0}, q[3] = {0, 0, 0}, r[3] = {0, 0, 0}, x[3] = {0, 0, 0}, P[9];
+  const int t = threadIdx.x;
+  const int i = w * kPcgBlock + t;
+  const int64_t f0 = int64_t(w) * (3 * kPcgBlock);  // first vector value of the workgroup
+  const int64_t nf = 3 * int64_t(N);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int64_t f = f0 + k * kPcgBlock + t;
+    if (f < nf) {
+      sq[k * kPcgBlock + t] = V.q[f];
+      sr[k * kPcgBlock + t] = V.r[f];
+      sx[k * kPcgBlock + t] = V.x[f];
+    }
+  }
+  double d[3] = {0, 0, 0}, P[9];
   if (i < N) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      d[c] = znext[6 * size_t(i) + 3 + c];
-      q[c] = V.q[3 * i + c];
-      r[c] = V.r[3 * i + c];
-      x[c] = V.x[3 * i + c];
-    }
+    for (int c = 0; c < 3; ++c) d[c] = znext[6 * size_t(i) + 3 + c];
 #pragma unroll
     for (int k = 0; k < 9; ++k) P[k] = double(__builtin_nontemporal_load(V.pinv + k * N + i));
   }
-  const double kap = reduce_partials(D.part + kPartKappa * Gp, Gp, lds);
+  const double kap = reduce_partials(D.part + kPartKappa * Gp, Gp, lds);  // synchronises
   if (kap <= 0.0) { pcg_finish(D, 1, j + 1); return; }
   const double alpha = D.pcg->rz[j & 1] / kap;
   double rr = 0.0, rzn = 0.0;
   if (i < N) {
+    double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      V.x[3 * i + c] = x[c] + alpha * d[c];
-      r[c] -= alpha * q[c];
-      V.r[3 * i + c] = r[c];
+      sx[3 * t + c] += alpha * d[c];
+      r[c] = sr[3 * t + c] - alpha * sq[3 * t + c];
+      sr[3 * t + c] = r[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -301,9 +315,17 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, in
       rr += r[c] * r[c];
     }
   }
-  rr = block_sum(rr, lds);
+  rr = block_sum(rr, lds);  // synchronises: sx and sr are complete
   rzn = block_sum(rzn, lds);
-  if (threadIdx.x == 0) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int64_t f = f0 + k * kPcgBlock + t;
+    if (f < nf) {
+      V.r[f] = sr[k * kPcgBlock + t];
+      V.x[f] = sx[k * kPcgBlock + t];
+    }
+  }
+  if (t == 0) {
     D.part[kPartRR * Gp + w] = rr;
     D.part[((j & 1) ? kPartRZ0 : kPartRZ1) * Gp + w] = rzn;
   }
