@@ -159,7 +159,8 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
   qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = M(0);
   // FP64 streams from HBM and runs best with one slot in flight per lane; the
   // cache-resident FP32 matrix gains from two (measured on the 1.57M-tet cube).
-#pragma unroll(sizeof(M) == 4 ? 2 : 1)
+  constexpr int kUnroll = sizeof(M) == 4 ? 2 : 1;
+#pragma unroll kUnroll
   for (int s = 0; s < S; ++s) {
     const int slot = s * D.n_groups + g;
     const int c = D.col[slot * kSell + l];
