@@ -142,6 +142,106 @@ def roofline(R, precision, info, cfg):
             "launches": tot["n_spmv"]}
 
 
+def _engine_scenes(engine, scenes, precision):
+    from paper_2505_21013_amd import PPN_MIXED
+    t = time.perf_counter()
+    ids = [engine.add_scene(sc, precision=PPN_MIXED if precision == "mixed" else 0) for sc in scenes]
+    print(f"registered {len(ids)} scenes in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    return ids
+
+
+def run_batch(a):
+    """64 independent scenes (rotated cubes and beams of 384..384k tets), mixed
+    form, K steps each, through the engine: one worker (scenes one after the
+    other) against --workers workers (scenes overlapping on the device)."""
+    import numpy as np
+    import torch
+    from paper_2505_21013_amd import Engine
+    from scenes import batch_scenes
+    torch.cuda.set_device(0)
+    scenes = batch_scenes()
+    K = min(a.steps, 20)
+    out = {"metric": "batched time steps/s (64 independent scenes, mixed form)", "unit": "steps/s",
+           "n_gpus": 1, "steps_per_scene": K, "dtype": "f32+f64", "data": "synthetic",
+           "higher_is_better": True,
+           "config": {"workload": f"64 rotated blocks, {sum(s.n_tets for s in scenes)} tets in total "
+                                  f"({min(s.n_tets for s in scenes)}..{max(s.n_tets for s in scenes)} per "
+                                  f"scene), steps 1..{K}, PPN", "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")}}
+    for workers in (1, a.workers):
+        with Engine(n_workers=workers) as e:
+            ids = _engine_scenes(e, scenes, "mixed")
+            warm = [e.ppn_engine_submit(sid, "PPN", sc.targets(1)) for sc, sid in zip(scenes, ids)]
+            for r in warm:
+                e.ppn_engine_wait(r)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reqs = [e.ppn_engine_submit(sid, "PPN", sc.targets(n)) for n in range(2, K + 2)
+                    for sc, sid in zip(scenes, ids)]
+            res = [e.ppn_engine_wait(r) for r in reqs]
+            el = time.perf_counter() - t0
+            ok = all(r["status"] in ("PPN_OK",) for r in res)
+            out[f"workers_{workers}"] = {"value": len(reqs) / el, "elapsed_s": el, "all_converged": ok,
+                                         "newton_iters": sum(r["newton_iters"] for r in res),
+                                         "pcg_iters": sum(r["pcg_iters"] for r in res)}
+            print(f"batch workers={workers}: {len(reqs) / el:.1f} steps/s", file=sys.stderr, flush=True)
+    out["value"] = out[f"workers_{a.workers}"]["value"]
+    out["speedup_vs_one_worker"] = out["value"] / out["workers_1"]["value"]
+    return out
+
+
+def run_serve(a):
+    """Serving loop: 128 resident scenes (1e3..5e5 tets, ~10M in total), one
+    warm-up step each, then --requests time-step requests with exponential
+    inter-arrival gaps (mean 1/--rate) on uniformly drawn scenes, submitted in
+    real time; latency = completion - arrival."""
+    import numpy as np
+    import torch
+    from paper_2505_21013_amd import Engine
+    from scenes import serving_scenes
+    torch.cuda.set_device(0)
+    scenes = serving_scenes()
+    rng = np.random.default_rng(4)
+    gaps = rng.exponential(1.0 / a.rate, size=a.requests)
+    which = rng.integers(len(scenes), size=a.requests)
+    with Engine(n_workers=a.workers) as e:
+        ids = _engine_scenes(e, scenes, "mixed")
+        step = [1] * len(scenes)
+        warm = [e.ppn_engine_submit(sid, "PPN", sc.targets(1)) for sc, sid in zip(scenes, ids)]
+        for r in warm:
+            e.ppn_engine_wait(r)
+        info0 = e.ppn_engine_get_info()
+        print(f"warm: {info0}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        due = t0
+        reqs = []
+        for g, k in zip(gaps, which):
+            due += g
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            step[k] += 1
+            reqs.append(e.ppn_engine_submit(ids[k], "PPN", scenes[k].targets(step[k])))
+        res = [e.ppn_engine_wait(r) for r in reqs]
+        el = time.perf_counter() - t0
+        info = e.ppn_engine_get_info()
+    lat = np.array([r["latency_ms"] for r in res])
+    que = np.array([r["queue_ms"] for r in res])
+    return {"metric": "served time-step requests/s; p50/p99 request latency (1 GPU)",
+            "value": len(res) / el, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"{len(scenes)} resident cubes, {sum(s.n_tets for s in scenes)} tets "
+                                   f"({min(s.n_tets for s in scenes)}..{max(s.n_tets for s in scenes)}), "
+                                   f"{a.requests} requests, Poisson {a.rate:g}/s, one PPN step each",
+                       "workers": a.workers, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
+            "offered_rate": a.rate, "elapsed_s": el,
+            "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+            "p50_queue_ms": float(np.percentile(que, 50)), "p99_queue_ms": float(np.percentile(que, 99)),
+            "all_ok": all(r["status"] in ("PPN_OK", "PPN_WARN_NOT_CONVERGED") for r in res),
+            "not_converged": sum(r["status"] != "PPN_OK" for r in res),
+            "resident_bytes": info["resident_bytes"], "resident_scenes": info["resident_scenes"],
+            "evictions": info["evictions"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +253,16 @@ def main():
                     help="fp64 or mixed alone, or both (FP64 headline, mixed reported beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stats-out", default=None, help="write per-step stats JSON here")
+    ap.add_argument("--batch", action="store_true",
+                    help="batched workload instead: 64 independent scenes through the serving engine")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload instead: Poisson time-step requests over 128 resident scenes")
+    ap.add_argument("--workers", type=int, default=8, help="engine worker threads (--batch / --serve)")
+    ap.add_argument("--hw-queues", type=int, default=4,
+                    help="--batch / --serve: HIP hardware queues of the process (at most 32; 4 measured "
+                         "best: 2.7x over one worker on the batch, 1.5x with 8 queues, 1.1x with 16)")
+    ap.add_argument("--requests", type=int, default=2000, help="--serve: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="--serve: mean arrival rate [1/s]")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 plain device copies of this many MiB (HBM counter calibration)")
     a = ap.parse_args()
@@ -160,6 +270,11 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
               "note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if a.batch or a.serve:
+        # HIP reads this at initialisation
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(1, min(32, a.hw_queues)))
+        print(json.dumps(run_batch(a) if a.batch else run_serve(a)), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -252,6 +252,74 @@ ppn_status ppn_energy_difference(ppn_scene* s, const double* x, const double* dx
 ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t n, double eps,
                                  void* hip_stream);
 
+/* ---- Serving engine ---------------------------------------------------------
+ * Many resident scenes stepped on request (time-step requests of uneven mesh
+ * sizes as they arrive).  n_workers host threads take requests in arrival
+ * order, skipping requests whose scene is busy; each resident scene has its
+ * own HIP stream, so requests of different scenes run concurrently and their
+ * kernels overlap on the device, while the requests of one scene run one at a
+ * time in submission order.  A scene is admitted to device memory when its
+ * footprint (exactly the bytes its buffers take) fits the budget; idle
+ * resident scenes are evicted least recently used first, their positions and
+ * velocities kept on the host until the scene is admitted again.  A scene's
+ * arithmetic does not depend on what else runs: every result is bit-identical
+ * to running the same requests alone.  The engine copies every input. */
+typedef struct ppn_engine ppn_engine; /* opaque */
+
+typedef struct {
+  int32_t n_verts, n_tets;
+  const double* rest_xyz;       /* [n_verts][3] */
+  const int32_t* tets;          /* [n_tets][4], positively oriented at rest */
+  const double* init_xyz;       /* [n_verts][3] or NULL (rest shape) */
+  const double* init_vel;       /* [n_verts][3] or NULL (zero) */
+  double rho;                   /* density [kg/m^3] */
+  const double* E;              /* Young's modulus [Pa]: [n_tets] if per_element, else [1] */
+  const double* nu;             /* Poisson ratio, same length as E */
+  int32_t per_element;
+  int32_t n_dirichlet;
+  const int32_t* dirichlet_ids; /* [n_dirichlet] distinct vertex ids */
+  double dt;                    /* time step [s] */
+  double gravity[3];            /* [m/s^2] */
+  int32_t precision;            /* ppn_precision */
+  int32_t reserved0;
+  const ppn_params* params;     /* NULL: ppn_params_default */
+} ppn_scene_desc;
+
+typedef struct {
+  int64_t budget_bytes;    /* device-memory budget for resident scenes */
+  int64_t resident_bytes;  /* footprint of the resident scenes */
+  int64_t admissions;      /* scene loads into device memory */
+  int64_t evictions;       /* scenes moved out to make room */
+  int32_t resident_scenes, n_scenes, n_workers, pending;
+} ppn_engine_info;
+
+/* Create an engine on the current HIP device.  mem_budget_bytes <= 0 means 90%
+ * of the device memory free at creation.  PPN_ERR_ARG unless 1 <= n_workers <= 256. */
+ppn_status ppn_engine_create(ppn_engine** out, int32_t n_workers, int64_t mem_budget_bytes);
+/* Waits for the running requests, drops the pending ones, frees everything. */
+ppn_status ppn_engine_destroy(ppn_engine* e);
+/* Register a scene (nothing is allocated on the device until its first
+ * request); validates the description and builds its block pattern on the host.
+ * PPN_ERR_MESH for an invalid mesh. */
+ppn_status ppn_engine_add_scene(ppn_engine* e, const ppn_scene_desc* d, int32_t* scene_id_out);
+/* Device bytes the scene takes while resident. */
+ppn_status ppn_engine_scene_footprint(ppn_engine* e, int32_t scene_id, int64_t* bytes_out);
+/* Queue one time step of scene_id in the given mode with the Dirichlet targets
+ * of that step ([n_dirichlet][3], copied).  Returns at once. */
+ppn_status ppn_engine_submit(ppn_engine* e, int32_t scene_id, int32_t mode, const double* targets,
+                             int64_t* request_id_out);
+/* Block until the request is done.  step_status_out receives the step's own
+ * status (PPN_OK, a warning, or the error that ended it, with the message in
+ * ppn_last_error(NULL) of the calling thread); stats_out its statistics;
+ * latency_ms_out the time from submission to completion and queue_ms_out the
+ * time it waited before a worker took it.  Any output may be NULL. */
+ppn_status ppn_engine_wait(ppn_engine* e, int64_t request_id, ppn_status* step_status_out,
+                           ppn_step_stats* stats_out, double* latency_ms_out, double* queue_ms_out);
+/* Positions and velocities [n_verts][3] of a scene once all its submitted
+ * requests are done (waits for them). */
+ppn_status ppn_engine_get_state(ppn_engine* e, int32_t scene_id, double* x_out, double* v_out);
+ppn_status ppn_engine_get_info(ppn_engine* e, ppn_engine_info* out);
+
 #ifdef __cplusplus
 }
 #endif

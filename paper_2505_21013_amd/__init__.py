@@ -12,9 +12,10 @@ import numpy as np
 
 from . import _abi
 from ._abi import (MODES, PPN_FP64, PPN_MIXED, PPN_PDN, PPN_PN, PPN_PPN, PPN_STOP_GRAD_REL,
-                   PPN_STOP_VEL, STATUS, ppn_iter_record, ppn_params, ppn_step_stats)
+                   PPN_STOP_VEL, STATUS, ppn_engine_info, ppn_iter_record, ppn_params,
+                   ppn_scene_desc, ppn_step_stats)
 
-__all__ = ["Scene", "PPNError", "ppn_params_default", "ppn_project_batch_dev", "ppn_params",
+__all__ = ["Scene", "Engine", "PPNError", "ppn_params_default", "ppn_project_batch_dev", "ppn_params",
            "ppn_step_stats", "ppn_iter_record", "MODES", "PPN_PN", "PPN_PDN", "PPN_PPN",
            "PPN_FP64", "PPN_MIXED", "PPN_STOP_VEL", "PPN_STOP_GRAD_REL", "library_path"]
 
@@ -267,6 +268,107 @@ class Scene:
         out = np.empty(g.size)
         self._c(_abi.lib().ppn_energy_difference(self._h, _d(x), _d(dx), g.size, _d(g), _d(out)))
         return out
+
+
+class Engine:
+    """Serving engine (``ppn_engine_*``): resident scenes stepped on request by
+    ``n_workers`` host threads, one HIP stream per resident scene."""
+
+    def __init__(self, n_workers=8, mem_budget_bytes=0):
+        h = C.c_void_p()
+        _check(_abi.lib().ppn_engine_create(C.byref(h), int(n_workers), int(mem_budget_bytes)))
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            _abi.lib().ppn_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def ppn_engine_add_scene(self, X, tets, E, nu, rho, dt, gravity, dirichlet_ids, precision=PPN_FP64,
+                             params=None, x0=None, v0=None):
+        X = _f64(X)
+        N = X.size // 3
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        E = _f64(E).reshape(-1)
+        nu = _f64(nu).reshape(-1)
+        ids = np.ascontiguousarray(dirichlet_ids, dtype=np.int32)
+        d = ppn_scene_desc()
+        d.n_verts, d.n_tets = N, tets.shape[0]
+        d.rest_xyz, d.tets = _d(X), _i(tets)
+        x0 = _f64(x0, 3 * N) if x0 is not None else None
+        v0 = _f64(v0, 3 * N) if v0 is not None else None
+        d.init_xyz, d.init_vel = _d(x0), _d(v0)
+        d.rho, d.E, d.nu, d.per_element = float(rho), _d(E), _d(nu), int(E.size > 1)
+        d.n_dirichlet, d.dirichlet_ids = ids.size, _i(ids)
+        d.dt = float(dt)
+        d.gravity[:] = [float(g) for g in gravity]
+        d.precision = int(precision)
+        p = None
+        if params is not None:
+            p = ppn_params_default()
+            for k, v in params.items():
+                setattr(p, k, v)
+            d.params = C.pointer(p)
+        sid = C.c_int32()
+        _check(_abi.lib().ppn_engine_add_scene(self._h, C.byref(d), C.byref(sid)))
+        return sid.value
+
+    def add_scene(self, sc, precision=PPN_FP64, params=None):
+        """Register a ``scenes.Scene`` (mesh, material, time step, constrained ids, initial state)."""
+        kw = dict(stop_mode=PPN_STOP_VEL if sc.stop_mode == "vel" else PPN_STOP_GRAD_REL,
+                  stop_tol=sc.stop_tol)
+        kw.update(params or {})
+        return self.ppn_engine_add_scene(sc.X, sc.tets, sc.E, sc.nu, sc.rho, sc.dt, sc.gravity,
+                                         sc.dirichlet_ids, precision, kw, sc.x0, sc.v0)
+
+    def ppn_engine_scene_footprint(self, scene_id):
+        b = C.c_int64()
+        _check(_abi.lib().ppn_engine_scene_footprint(self._h, int(scene_id), C.byref(b)))
+        return b.value
+
+    def ppn_engine_submit(self, scene_id, mode, targets):
+        t = _f64(targets)
+        rid = C.c_int64()
+        _check(_abi.lib().ppn_engine_submit(self._h, int(scene_id), MODES[mode], _d(t), C.byref(rid)))
+        return rid.value
+
+    def ppn_engine_wait(self, request_id):
+        st = C.c_int()
+        stats = ppn_step_stats()
+        lat, que = C.c_double(), C.c_double()
+        _check(_abi.lib().ppn_engine_wait(self._h, int(request_id), C.byref(st), C.byref(stats),
+                                           C.byref(lat), C.byref(que)))
+        d = stats.as_dict()
+        d["status"] = STATUS.get(st.value, st.value)
+        if st.value < 0:
+            msg = _abi.lib().ppn_last_error(None)
+            d["error"] = msg.decode() if msg else ""
+        d["latency_ms"], d["queue_ms"] = lat.value, que.value
+        return d
+
+    def ppn_engine_get_state(self, scene_id, n_verts):
+        x = np.empty((n_verts, 3))
+        v = np.empty((n_verts, 3))
+        _check(_abi.lib().ppn_engine_get_state(self._h, int(scene_id), _d(x), _d(v)))
+        return x, v
+
+    def ppn_engine_get_info(self):
+        i = ppn_engine_info()
+        _check(_abi.lib().ppn_engine_get_info(self._h, C.byref(i)))
+        return i.as_dict()
 
 
 def scene_from(sc, stream=None, params=None, trace=False, precision=PPN_FP64):

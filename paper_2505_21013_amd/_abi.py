@@ -44,6 +44,26 @@ class ppn_iter_record(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ppn_scene_desc(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("n_tets", C.c_int32), ("rest_xyz", C.POINTER(C.c_double)),
+                ("tets", C.POINTER(C.c_int32)), ("init_xyz", C.POINTER(C.c_double)),
+                ("init_vel", C.POINTER(C.c_double)), ("rho", C.c_double),
+                ("E", C.POINTER(C.c_double)), ("nu", C.POINTER(C.c_double)),
+                ("per_element", C.c_int32), ("n_dirichlet", C.c_int32),
+                ("dirichlet_ids", C.POINTER(C.c_int32)), ("dt", C.c_double),
+                ("gravity", C.c_double * 3), ("precision", C.c_int32), ("reserved0", C.c_int32),
+                ("params", C.POINTER(ppn_params))]
+
+
+class ppn_engine_info(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("resident_bytes", C.c_int64), ("admissions", C.c_int64),
+                ("evictions", C.c_int64), ("resident_scenes", C.c_int32), ("n_scenes", C.c_int32),
+                ("n_workers", C.c_int32), ("pending", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 P = C.c_void_p
 dp = C.POINTER(C.c_double)
 ip = C.POINTER(C.c_int32)
@@ -80,6 +100,14 @@ SIGNATURES = {
     "ppn_hessian_product": (C.c_int, [P, dp, u8p, dp, dp]),
     "ppn_energy_difference": (C.c_int, [P, dp, dp, C.c_int32, dp, dp]),
     "ppn_project_batch_dev": (C.c_int, [P, P, C.c_int64, C.c_double, P]),
+    "ppn_engine_create": (C.c_int, [C.POINTER(P), C.c_int32, C.c_int64]),
+    "ppn_engine_destroy": (C.c_int, [P]),
+    "ppn_engine_add_scene": (C.c_int, [P, C.POINTER(ppn_scene_desc), ip]),
+    "ppn_engine_scene_footprint": (C.c_int, [P, C.c_int32, i64p]),
+    "ppn_engine_submit": (C.c_int, [P, C.c_int32, C.c_int32, dp, i64p]),
+    "ppn_engine_wait": (C.c_int, [P, C.c_int64, C.POINTER(C.c_int), C.POINTER(ppn_step_stats), dp, dp]),
+    "ppn_engine_get_state": (C.c_int, [P, C.c_int32, dp, dp]),
+    "ppn_engine_get_info": (C.c_int, [P, C.POINTER(ppn_engine_info)]),
 }
 
 _lib = None

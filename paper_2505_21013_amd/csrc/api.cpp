@@ -5,14 +5,15 @@
 #include <string>
 
 #include "../../include/ppn.h"
+#include "engine.h"
 #include "scene.h"
-
-namespace ppn {
-void params_defaults(ppn_params* p);
-}
 
 struct ppn_scene {
   ppn::Scene* impl = nullptr;
+};
+
+struct ppn_engine {
+  ppn::Engine* impl = nullptr;
 };
 
 namespace {
@@ -313,6 +314,116 @@ ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t 
     return PPN_ERR_DEVICE;
   }
   return PPN_OK;
+}
+
+// ---- serving engine
+#define ENGINE(e)                                  \
+  if (!(e) || !(e)->impl) {                        \
+    g_error = "NULL engine handle";                \
+    return PPN_ERR_ARG;                            \
+  }                                                \
+  ppn::Engine& EG = *(e)->impl
+
+ppn_status ppn_engine_create(ppn_engine** out, int32_t n_workers, int64_t mem_budget_bytes) {
+  if (!out) {
+    g_error = "out must not be NULL";
+    return PPN_ERR_ARG;
+  }
+  *out = nullptr;
+  if (n_workers < 1 || n_workers > 256) {
+    g_error = "n_workers must be in [1, 256]";
+    return PPN_ERR_ARG;
+  }
+  return guarded(nullptr, [&]() -> ppn_status {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) throw ppn::HipError{std::string("hipGetDevice: ") + hipGetErrorString(e), PPN_ERR_DEVICE};
+    auto* h = new ppn_engine;
+    try {
+      h->impl = new ppn::Engine(dev, n_workers, mem_budget_bytes);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return PPN_OK;
+  });
+}
+
+ppn_status ppn_engine_destroy(ppn_engine* e) {
+  if (!e) return PPN_OK;
+  delete e->impl;
+  delete e;
+  return PPN_OK;
+}
+
+ppn_status ppn_engine_add_scene(ppn_engine* e, const ppn_scene_desc* d, int32_t* scene_id_out) {
+  ENGINE(e);
+  if (!d || !scene_id_out) {
+    g_error = "desc and scene_id_out must not be NULL";
+    return PPN_ERR_ARG;
+  }
+  return guarded(nullptr, [&]() -> ppn_status {
+    *scene_id_out = EG.add_scene(*d);
+    return PPN_OK;
+  });
+}
+
+ppn_status ppn_engine_scene_footprint(ppn_engine* e, int32_t scene_id, int64_t* bytes_out) {
+  ENGINE(e);
+  if (!bytes_out) {
+    g_error = "bytes_out must not be NULL";
+    return PPN_ERR_ARG;
+  }
+  return guarded(nullptr, [&]() -> ppn_status {
+    *bytes_out = EG.footprint(scene_id);
+    return PPN_OK;
+  });
+}
+
+ppn_status ppn_engine_submit(ppn_engine* e, int32_t scene_id, int32_t mode, const double* targets,
+                             int64_t* request_id_out) {
+  ENGINE(e);
+  if (!request_id_out) {
+    g_error = "request_id_out must not be NULL";
+    return PPN_ERR_ARG;
+  }
+  return guarded(nullptr, [&]() -> ppn_status {
+    *request_id_out = EG.submit(scene_id, mode, targets);
+    return PPN_OK;
+  });
+}
+
+ppn_status ppn_engine_wait(ppn_engine* e, int64_t request_id, ppn_status* step_status_out,
+                           ppn_step_stats* stats_out, double* latency_ms_out, double* queue_ms_out) {
+  ENGINE(e);
+  return guarded(nullptr, [&]() -> ppn_status {
+    std::string err;
+    const ppn_status st = EG.wait(request_id, stats_out, latency_ms_out, queue_ms_out, &err);
+    if (!err.empty()) g_error = err;
+    if (step_status_out) *step_status_out = st;
+    return PPN_OK;
+  });
+}
+
+ppn_status ppn_engine_get_state(ppn_engine* e, int32_t scene_id, double* x_out, double* v_out) {
+  ENGINE(e);
+  return guarded(nullptr, [&]() -> ppn_status {
+    EG.get_state(scene_id, x_out, v_out);
+    return PPN_OK;
+  });
+}
+
+ppn_status ppn_engine_get_info(ppn_engine* e, ppn_engine_info* out) {
+  ENGINE(e);
+  if (!out) {
+    g_error = "out must not be NULL";
+    return PPN_ERR_ARG;
+  }
+  return guarded(nullptr, [&]() -> ppn_status {
+    EG.info(out);
+    return PPN_OK;
+  });
 }
 
 }  // extern "C"

@@ -94,84 +94,129 @@ void Scene::read_scal(int n, double* out) {
 }
 
 // ---------------------------------------------------------------- set-up
+// Launch geometry of a scene from its topology.
+static void geometry(Dev& D, const Topology& t) {
+  const int N = t.n_verts, T = t.n_tets;
+  D.N = N;
+  D.T = T;
+  D.E = t.n_edges;
+  D.NB = t.n_blocks;
+  int G = (N + 127) / 128;
+  G = std::min(2048, std::max(8, ((G + 7) / 8) * 8));
+  D.G = G;
+  D.rows_per_wg = (((N + G - 1) / G) + 15) / 16 * 16;
+  D.n_sel_wg = (T + kBlock - 1) / kBlock;
+  // PCG kernels: one row per thread, one 64-row group per wavefront, four
+  // groups per 256-thread workgroup, a multiple of 8 workgroups (one per XCD).
+  D.n_groups = t.n_groups;
+  D.n_slots = t.n_slots;
+  D.Gp = ((D.n_groups + 3) / 4 + 7) / 8 * 8;
+}
+
+// Every device buffer of a scene, in one place.  A::get<T>(count) either
+// allocates or only counts the bytes (footprint()).
+template <class A>
+static void plan_buffers(Dev& D, int precision, A& alloc) {
+  const size_t n = size_t(D.N), m = size_t(D.T);
+  D.tets = alloc.template get<int32_t>(4 * m);
+  D.Bm = alloc.template get<double>(9 * m);
+  D.vol = alloc.template get<double>(m);
+  D.mu = alloc.template get<double>(m);
+  D.lam = alloc.template get<double>(m);
+  D.Eyoung = alloc.template get<double>(m);
+  D.nu = alloc.template get<double>(m);
+  D.mass = alloc.template get<double>(n);
+  D.X = alloc.template get<double>(3 * n);
+  D.vslot = alloc.template get<int32_t>(4 * m);
+  D.eslot = alloc.template get<int32_t>(6 * m);
+  D.elem_edge = alloc.template get<int32_t>(6 * m);
+  D.vptr = alloc.template get<int32_t>(n + 1);
+  D.vslot_elem = alloc.template get<int32_t>(4 * m);
+  D.eptr = alloc.template get<int32_t>(size_t(D.E) + 1);
+  D.gslots = alloc.template get<int32_t>(size_t(D.n_groups));
+  D.col = alloc.template get<int32_t>(size_t(D.n_slots) * kSell);
+  D.diag_blk = alloc.template get<int32_t>(n);
+  D.eblk_up = alloc.template get<int32_t>(size_t(D.E));
+  D.eblk_lo = alloc.template get<int32_t>(size_t(D.E));
+  D.vslots = alloc.template get<double>(4 * m * 9);
+  D.eslots = alloc.template get<double>(6 * m * 9);
+  D.vals = alloc.template get<double>(size_t(D.n_slots) * 9 * kSell);
+  D.pinv = alloc.template get<double>(9 * n);
+  D.spd_ok = alloc.template get<uint8_t>(n);
+  D.dir_idx = alloc.template get<int32_t>(n);
+  D.xbar = alloc.template get<double>(3 * n);
+  double** vecs[] = {&D.x, &D.xn, &D.v, &D.xhat, &D.g, &D.dx, &D.r, &D.q, &D.xt};
+  for (double** p : vecs) *p = alloc.template get<double>(3 * n);
+  D.zd = alloc.template get<double>(12 * n);
+  D.rinf = alloc.template get<double>(n);
+  if (precision == PPN_MIXED) {
+    D.vals32 = alloc.template get<float>(size_t(D.n_slots) * 9 * kSell);
+    D.pinv32 = alloc.template get<float>(9 * n);
+    D.e = alloc.template get<double>(3 * n);
+    D.ri = alloc.template get<double>(3 * n);
+    D.qi = alloc.template get<double>(3 * n);
+  }
+  D.proj = alloc.template get<uint8_t>(m);
+  D.sel = alloc.template get<uint8_t>(m);
+  D.list = alloc.template get<int32_t>(m);
+  D.sel_cnt = alloc.template get<int32_t>(size_t(D.n_sel_wg) + 1);
+  D.part = alloc.template get<double>(size_t(kPartCount) * std::max(D.G, D.Gp));
+  D.scal = alloc.template get<double>(16);
+  D.pcg = alloc.template get<PcgState>(1);
+  D.flag = alloc.template get<int32_t>(4);
+}
+
+struct CountBytes {
+  int64_t bytes = 0;
+  template <class T>
+  T* get(size_t n) {
+    bytes += int64_t(std::max<size_t>(n, 1) * sizeof(T));
+    return nullptr;
+  }
+};
+
+struct DeviceAlloc {
+  Scene* s;
+  template <class T>
+  T* get(size_t n) { return s->alloc<T>(n); }
+};
+
+int64_t Scene::footprint(const Topology& t, int precision) {
+  Dev D;
+  geometry(D, t);
+  CountBytes c;
+  plan_buffers(D, precision, c);
+  return c.bytes;
+}
+
 void Scene::load_mesh(int32_t N, const double* rest, int32_t T, const int32_t* tets,
                       const double* init) {
   if (!rest || !tets) fail("rest_xyz and tets must not be NULL");
   Topology t;
   std::string err;
   if (!build_topology(N, T, tets, t, err)) fail(err, PPN_ERR_MESH);
+  load_mesh(std::move(t), rest, tets, init);
+}
+
+void Scene::load_mesh(Topology&& t, const double* rest, const int32_t* tets, const double* init) {
+  if (!rest || !tets) fail("rest_xyz and tets must not be NULL");
   if (loaded()) {
     sync();
     free_all();
   }
   topo_ = std::move(t);
+  const int32_t N = topo_.n_verts, T = topo_.n_tets;
   try {
     Dev D;
-    D.N = N;
-    D.T = T;
-    D.E = topo_.n_edges;
-    D.NB = topo_.n_blocks;
-    int G = (N + 127) / 128;
-    G = std::min(2048, std::max(8, ((G + 7) / 8) * 8));
-    D.G = G;
-    D.rows_per_wg = (((N + G - 1) / G) + 15) / 16 * 16;
-    D.n_sel_wg = (T + kBlock - 1) / kBlock;
-    // PCG kernels: one row per thread, one 64-row group per wavefront; up to 8
-    // wavefronts per workgroup once there are enough groups to keep every CU busy.
-    D.n_groups = topo_.n_groups;
-    D.n_slots = topo_.n_slots;
-    D.Gp = ((D.n_groups + 3) / 4 + 7) / 8 * 8;
+    geometry(D, topo_);
     D.h = D_.h;
     D.k_dir = prm_.k_dirichlet;
     std::memcpy(D.grav, D_.grav, sizeof(D.grav));
     D_ = D;
     const size_t n = size_t(N), m = size_t(T);
-    D_.tets = alloc<int32_t>(4 * m);
-    D_.Bm = alloc<double>(9 * m);
-    D_.vol = alloc<double>(m);
-    D_.mu = alloc<double>(m);
-    D_.lam = alloc<double>(m);
-    D_.Eyoung = alloc<double>(m);
-    D_.nu = alloc<double>(m);
-    D_.mass = alloc<double>(n);
-    D_.X = alloc<double>(3 * n);
-    D_.vslot = alloc<int32_t>(4 * m);
-    D_.eslot = alloc<int32_t>(6 * m);
-    D_.elem_edge = alloc<int32_t>(6 * m);
-    D_.vptr = alloc<int32_t>(n + 1);
-    D_.vslot_elem = alloc<int32_t>(4 * m);
-    D_.eptr = alloc<int32_t>(size_t(D_.E) + 1);
-    D_.gslots = alloc<int32_t>(size_t(D_.n_groups));
-    D_.col = alloc<int32_t>(size_t(D_.n_slots) * kSell);
-    D_.diag_blk = alloc<int32_t>(n);
-    D_.eblk_up = alloc<int32_t>(size_t(D_.E));
-    D_.eblk_lo = alloc<int32_t>(size_t(D_.E));
-    D_.vslots = alloc<double>(4 * m * 9);
-    D_.eslots = alloc<double>(6 * m * 9);
-    D_.vals = alloc<double>(size_t(D_.n_slots) * 9 * kSell);
-    D_.pinv = alloc<double>(9 * n);
-    D_.spd_ok = alloc<uint8_t>(n);
-    D_.dir_idx = alloc<int32_t>(n);
-    D_.xbar = alloc<double>(3 * n);
-    double** vecs[] = {&D_.x, &D_.xn, &D_.v, &D_.xhat, &D_.g, &D_.dx, &D_.r, &D_.q, &D_.xt};
-    for (double** p : vecs) *p = alloc<double>(3 * n);
-    D_.zd = alloc<double>(12 * n);
-    D_.rinf = alloc<double>(n);
-    if (precision_ == PPN_MIXED) {
-      D_.vals32 = alloc<float>(size_t(D_.n_slots) * 9 * kSell);
-      D_.pinv32 = alloc<float>(9 * n);
-      D_.e = alloc<double>(3 * n);
-      D_.ri = alloc<double>(3 * n);
-      D_.qi = alloc<double>(3 * n);
-    }
-    D_.proj = alloc<uint8_t>(m);
-    D_.sel = alloc<uint8_t>(m);
-    D_.list = alloc<int32_t>(m);
-    D_.sel_cnt = alloc<int32_t>(size_t(D_.n_sel_wg) + 1);
-    D_.part = alloc<double>(size_t(kPartCount) * std::max(G, D_.Gp));
-    D_.scal = alloc<double>(16);
-    D_.pcg = alloc<PcgState>(1);
-    D_.flag = alloc<int32_t>(4);
+    DeviceAlloc da{this};
+    plan_buffers(D_, precision_, da);
+    if (dev_bytes_ != footprint(topo_, precision_)) fail("internal: footprint mismatch", PPN_ERR_DEVICE);
 
     std::vector<int32_t> soa(4 * m);
     for (size_t e = 0; e < m; ++e)

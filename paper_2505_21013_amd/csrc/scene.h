@@ -12,6 +12,9 @@
 
 namespace ppn {
 
+// Defaults of every parameter (the paper's values).
+void params_defaults(ppn_params* p);
+
 struct HipError {
   std::string msg;
   ppn_status code;
@@ -24,6 +27,12 @@ class Scene {
 
   void load_mesh(int32_t n_verts, const double* rest, int32_t n_tets, const int32_t* tets,
                  const double* init);
+  // Same with a topology built beforehand (build_topology on the same tets).
+  void load_mesh(Topology&& t, const double* rest, const int32_t* tets, const double* init);
+  // Device bytes a scene of this topology allocates (exactly what load_mesh takes).
+  static int64_t footprint(const Topology& t, int precision);
+  template <class T>
+  T* alloc(size_t n);
   void set_material(double rho, const double* E, const double* nu, bool per_element);
   void set_time_step(double dt, const double* gravity);
   void set_dirichlet(int32_t n, const int32_t* ids, const double* targets);
@@ -60,8 +69,6 @@ class Scene {
   std::vector<std::vector<int32_t>> trace_ids;
 
  private:
-  template <class T>
-  T* alloc(size_t n);
   void free_all();
   void upload_material();
   void upload_dirichlet();

@@ -175,13 +175,88 @@ def cube_compress(n=64, L=1.0, E_lo=1e4, E_hi=1e6, nu=0.48, rho=1000.0, dt=1.0 /
                  meta=dict(cells=(n, n, n), size=(L, L, L)))
 
 
-def config(k: int, **kw) -> Scene:
+def block_rotate(nx, ny, nz, cell, axis, angle, E=1e5, nu=0.45, rho=1000.0, dt=1.0 / 30.0,
+                 ramp_steps=20, name="block") -> Scene:
+    """Block of nx*ny*nz cells of edge ``cell``; the x = 0 face is pinned and
+    the opposite face is driven to c + R(axis, theta_n)(X - c), c its centre,
+    theta_n = angle * min(1, n / ramp_steps) (Rodrigues' rotation about the
+    unit ``axis``)."""
+    size = (nx * cell, ny * cell, nz * cell)
+    X, tets = kuhn_grid(nx, ny, nz, size=size)
+    left = _face(X, 0, 0.0)
+    right = _face(X, 0, size[0], atol=1e-9 * size[0])
+    ids = np.sort(np.concatenate([left, right])).astype(np.int32)
+    base = X[ids].copy()
+    is_right = np.isin(ids, right)
+    c = np.array([size[0], size[1] / 2, size[2] / 2])
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+
+    def targets(step):
+        th = angle * min(1.0, step / ramp_steps)
+        r = base[is_right] - c
+        ct, st = math.cos(th), math.sin(th)
+        rot = r * ct + np.cross(a, r) * st + np.outer(r @ a, a) * (1.0 - ct)
+        t = base.copy()
+        t[is_right] = c + rot
+        return t
+
+    T = tets.shape[0]
+    return Scene(name=name, X=X, tets=tets, x0=X.copy(), v0=np.zeros_like(X),
+                 E=np.full(T, E), nu=np.full(T, nu), rho=rho, dt=dt, gravity=GRAVITY,
+                 dirichlet_ids=ids, targets=targets, n_steps=ramp_steps, stop_mode="vel",
+                 stop_tol=1e-3, meta=dict(cells=(nx, ny, nz), size=size, axis=tuple(a),
+                                          angle=angle))
+
+
+def batch_scenes(n_scenes=64, seed=3, n_lo=4, n_hi=40, ramp_steps=20):
+    """Independent scenes for batched stepping: n = round(n_lo (n_hi/n_lo)^U)
+    cells per side, a cube n^3 or a beam n x ceil(n/4) x ceil(n/4) (coin flip)
+    with cells of 1/n m, E 1e5 Pa, nu 0.45, rho 1000, h 1/30; the x = 0 face
+    pinned and the far face rotated about a random unit axis through its
+    centre by a total angle U(0, pi) over ``ramp_steps`` steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_scenes):
+        n = int(round(n_lo * (n_hi / n_lo) ** rng.uniform()))
+        beam = bool(rng.integers(2))
+        axis = rng.standard_normal(3)
+        angle = float(rng.uniform(0.0, math.pi))
+        dims = (n, -(-n // 4), -(-n // 4)) if beam else (n, n, n)
+        out.append(block_rotate(*dims, cell=1.0 / n, axis=axis, angle=angle, ramp_steps=ramp_steps,
+                                name=f"s{k}_{'beam' if beam else 'cube'}{n}"))
+    return out
+
+
+def serving_scenes(n_scenes=128, seed=4, t_lo=1e3, t_hi=5e5, ramp_steps=20):
+    """Resident scenes for the serving loop: target tet counts log-uniform in
+    [t_lo, t_hi], cubes of n = round((T/6)^(1/3)) cells of 1/n m, material and
+    constraints as in batch_scenes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_scenes):
+        T = math.exp(rng.uniform(math.log(t_lo), math.log(t_hi)))
+        n = max(1, int(round((T / 6.0) ** (1.0 / 3.0))))
+        axis = rng.standard_normal(3)
+        angle = float(rng.uniform(0.0, math.pi))
+        out.append(block_rotate(n, n, n, cell=1.0 / n, axis=axis, angle=angle, ramp_steps=ramp_steps,
+                                name=f"r{k}_cube{n}"))
+    return out
+
+
+def config(k: int, **kw):
     """The workload configurations by index: 0 small parity cube, 1 twisted
-    beam (122,880 tets), 2 compressed heterogeneous cube (1,572,864 tets)."""
+    beam (122,880 tets), 2 compressed heterogeneous cube (1,572,864 tets),
+    3 a batch of 64 independent scenes (a list), 4 the 128 resident scenes of
+    the serving loop (a list)."""
     if k == 0:
         return cube_jitter(**kw)
     if k == 1:
         return beam_twist(**kw)
     if k == 2:
         return cube_compress(**kw)
+    if k == 3:
+        return batch_scenes(**kw)
+    if k == 4:
+        return serving_scenes(**kw)
     raise ValueError(f"unknown configuration {k}")
