@@ -242,6 +242,47 @@ def run_serve(a):
             "evictions": info["evictions"]}
 
 
+def run_ablation(a):
+    """Variants of the paper on the compressed heterogeneous cube at 32^3 cells
+    (196,608 tets, FP64): steps 1..20 of the 50-step schedule in PPN give a
+    state at 24% compression with indefinite elements; from that state each
+    variant runs steps 21..30.  (The twisted beam is no use here: its global
+    Hessian stays positive definite through the schedule, so PPN and PDN never
+    project.)  Reported per variant: Newton and PCG iterations, projected
+    element Hessians and wall time."""
+    import numpy as np
+    import torch
+    from paper_2505_21013_amd import run_steps, scene_from
+    from scenes import cube_compress
+    torch.cuda.set_device(0)
+    sc = cube_compress(n=32)
+    stream = torch.cuda.current_stream().cuda_stream
+    s = scene_from(sc, stream=stream)
+    run_steps(s, sc, "PPN", 20)
+    x0, v0 = s.ppn_get_state()
+    variants = [("PPN", dict(alpha=al, beta=be)) for al in (0.25, 0.5, 0.75) for be in (1.0, 2.0, 4.0)]
+    variants += [("PDN", dict(pdn_countdown=c)) for c in (1, 4, 8)]
+    variants += [("PN", {})]
+    variants += [(m, dict(eig_mirror=1)) for m in ("PN", "PDN", "PPN")]
+    rows = []
+    for mode, kw in variants:
+        s.ppn_set_params(stop_mode=sc.stop_mode, stop_tol=sc.stop_tol, **kw)
+        s.ppn_set_state(x0, v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = run_steps(s, sc, mode, 10, first_step=21)
+        el = time.perf_counter() - t0
+        rows.append({"mode": mode, **kw, "newton_iters": sum(q["newton_iters"] for q in st),
+                     "pcg_iters": sum(q["pcg_iters"] for q in st), "projected": sum(q["projected"] for q in st),
+                     "converged_steps": sum(q["status"] == "PPN_OK" for q in st), "seconds": el})
+        print(rows[-1], file=sys.stderr, flush=True)
+    s.close()
+    return {"metric": "paper variants on the compressed cube, steps 21..30 from one state (FP64)",
+            "config": {"workload": f"cube 32^3 cells -> {sc.n_tets} tets, E log-uniform [1e4,1e6], nu 0.48, "
+                                   "top pushed down 60% over 50 steps, state after 20 PPN steps"},
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +298,8 @@ def main():
                     help="batched workload instead: 64 independent scenes through the serving engine")
     ap.add_argument("--serve", action="store_true",
                     help="serving workload instead: Poisson time-step requests over 128 resident scenes")
+    ap.add_argument("--ablation", action="store_true",
+                    help="paper variants instead: alpha/beta grid, PDN countdowns, mirroring (twisted beam)")
     ap.add_argument("--workers", type=int, default=8, help="engine worker threads (--batch / --serve)")
     ap.add_argument("--hw-queues", type=int, default=4,
                     help="--batch / --serve: HIP hardware queues of the process (at most 32; 4 measured "
@@ -270,6 +313,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
               "note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if a.ablation:
+        print(json.dumps(run_ablation(a)), flush=True)
+        return
     if a.batch or a.serve:
         # HIP reads this at initialisation
         os.environ["GPU_MAX_HW_QUEUES"] = str(max(1, min(32, a.hw_queues)))

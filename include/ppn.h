@@ -85,7 +85,8 @@ typedef struct {
   double stop_tol;
   double armijo_c;
   int32_t ls_maxit;
-  int32_t reserved0;
+  int32_t eig_mirror;    /* 0: clamp eigenvalues to max(lambda, eps) (Eq. (4)); 1: mirror them,
+                            max(|lambda|, eps) (the alternative filter of Sec. 2 and Sec. 5) */
   double k_dirichlet;   /* penalty stiffness [N/m] */
 } ppn_params;
 

@@ -60,6 +60,7 @@ class Params:
     beta: float = 2.0           # release factor (Sec. 4)
     eps_delta: float = 1e-12    # PN fallback threshold (Sec. 4)
     eps_clamp: float = 1e-8     # eigenvalue clamp (Sec. 5.1)
+    eig_mirror: bool = False    # mirror instead of clamp (Sec. 2, Sec. 5)
     pcg_rtol: float = 1e-4      # Sec. 5.1
     pcg_maxit: int = 10000
     pdn_countdown: int = 4      # Sec. 5.1
@@ -145,7 +146,7 @@ class Stepper:
             pm[np.asarray(projected, dtype=np.int64)] = True
             sel = pm[inc]
             if sel.any():
-                He[sel] = project_to_pd(He[sel], self.p.eps_clamp)
+                He[sel] = project_to_pd(He[sel], self.p.eps_clamp, self.p.eig_mirror)
         d = np.asarray(d, dtype=np.float64).reshape(-1, 3)
         ye = np.einsum("tpq,tq->tp", He, d[tets[inc]].reshape(-1, 12)).reshape(-1, 4, 3)
         out = np.zeros((self.mesh.n_verts, 3))
@@ -207,7 +208,7 @@ class Stepper:
                 sel = np.asarray(sel, dtype=np.int64)
                 if sel.size == 0:
                     return
-                Hhat = project_to_pd(He[sel], p.eps_clamp)
+                Hhat = project_to_pd(He[sel], p.eps_clamp, p.eig_mirror)
                 state["H"] = state["H"] + self.asm.hessian(Hhat - He[sel], None, idx=sel)
                 projected[sel] = True
                 st.projected += sel.size

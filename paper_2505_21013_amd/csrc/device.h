@@ -137,11 +137,12 @@ void launch_reduce_pcg(const Dev& D, int first_slot, int n_sum, hipStream_t st);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 void launch_select_count(const Dev& D, double delta, int fallback, hipStream_t st);
 void launch_select_write(const Dev& D, hipStream_t st);
-void launch_eig_all(const Dev& D, double eps, hipStream_t st);
-void launch_eig_list(const Dev& D, int32_t n, double eps, hipStream_t st);
+// mirror = 0: eigenvalues clamped to max(lambda, eps); 1: max(|lambda|, eps).
+void launch_eig_all(const Dev& D, double eps, int mirror, hipStream_t st);
+void launch_eig_list(const Dev& D, int32_t n, double eps, int mirror, hipStream_t st);
 // FP32 eigensolves (mixed precision); the slots stay FP64.
-void launch_eig_all_f32(const Dev& D, double eps, hipStream_t st);
-void launch_eig_list_f32(const Dev& D, int32_t n, double eps, hipStream_t st);
+void launch_eig_all_f32(const Dev& D, double eps, int mirror, hipStream_t st);
+void launch_eig_list_f32(const Dev& D, int32_t n, double eps, int mirror, hipStream_t st);
 void launch_regather_list(const Dev& D, int32_t n, hipStream_t st);
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st);
 // r = sign * src (FP64 source), x = 0, first preconditioned residual.

@@ -189,7 +189,7 @@ __device__ __forceinline__ void delta_block(int b, const T* dk, double eps, doub
 
 // Projection of one element.
 template <typename T, class IO>
-__device__ __forceinline__ void project_one(const IO& io, double eps) {
+__device__ __forceinline__ void project_one(const IO& io, double eps, bool mirror) {
   EigLane<T> L;
 #pragma unroll
   for (int i = 0; i < 45; ++i) L.a[i] = T(0);
@@ -216,10 +216,15 @@ __device__ __forceinline__ void project_one(const IO& io, double eps) {
     if (__all(done)) break;
     Sweep<0>::run(L);
   }
-  // Delta K = V W V^T with W = diag(max(eps - lambda_i, 0)).
+  // Delta K = V W V^T with W = diag(lambda_hat_i - lambda_i): lambda_hat =
+  // max(lambda, eps) when clamping, max(|lambda|, eps) when mirroring; both
+  // leave every lambda >= eps exactly unchanged (w = 0).
   T w[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) w[i] = fmax(T(eps) - L.a[ui9(i, i)], T(0));
+  for (int i = 0; i < 9; ++i) {
+    const T l = L.a[ui9(i, i)];
+    w[i] = mirror ? fmax(fabs(l), T(eps)) - l : fmax(T(eps) - l, T(0));
+  }
 #pragma unroll
   for (int r = 0; r < 9; ++r)
 #pragma unroll
@@ -335,19 +340,19 @@ struct Guarded {
 // Lanes past the end still take part in the wavefront's sweep vote: they work
 // on the first element's data in registers and never store.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_eig_all(Dev D, double eps) {
+__global__ __launch_bounds__(kBlock) void k_eig_all(Dev D, double eps, int mirror) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
   const bool live = e < D.T;
   SlotIO io(D, live ? e : 0);
-  project_one<T>(Guarded<SlotIO>{io, live}, eps);
+  project_one<T>(Guarded<SlotIO>{io, live}, eps, mirror != 0);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_eig_list(Dev D, int n, double eps) {
+__global__ __launch_bounds__(kBlock) void k_eig_list(Dev D, int n, double eps, int mirror) {
   const int k = blockIdx.x * kBlock + threadIdx.x;
   const bool live = k < n;
   SlotIO io(D, D.list[live ? k : 0]);
-  project_one<T>(Guarded<SlotIO>{io, live}, eps);
+  project_one<T>(Guarded<SlotIO>{io, live}, eps, mirror != 0);
 }
 
 template <typename T>
@@ -357,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_eig_dense(const double* in, double* 
   const bool live = k < n;
   const int64_t m = live ? k : 0;
   DenseIO io{in + 144 * m, out + 144 * m};
-  project_one<T>(Guarded<DenseIO>{io, live}, eps);
+  project_one<T>(Guarded<DenseIO>{io, live}, eps, false);
 }
 
 // Full 12x12 element matrices gathered from the slots (debug / parity output).
@@ -376,22 +381,22 @@ __global__ __launch_bounds__(kBlock) void k_elem_dense(Dev D, const int32_t* ids
   }
 }
 
-void launch_eig_all(const Dev& D, double eps, hipStream_t st) {
-  k_eig_all<double><<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, eps);
+void launch_eig_all(const Dev& D, double eps, int mirror, hipStream_t st) {
+  k_eig_all<double><<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, eps, mirror);
 }
 
-void launch_eig_list(const Dev& D, int32_t n, double eps, hipStream_t st) {
+void launch_eig_list(const Dev& D, int32_t n, double eps, int mirror, hipStream_t st) {
   if (n <= 0) return;
-  k_eig_list<double><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps);
+  k_eig_list<double><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps, mirror);
 }
 
-void launch_eig_all_f32(const Dev& D, double eps, hipStream_t st) {
-  k_eig_all<float><<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, eps);
+void launch_eig_all_f32(const Dev& D, double eps, int mirror, hipStream_t st) {
+  k_eig_all<float><<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, eps, mirror);
 }
 
-void launch_eig_list_f32(const Dev& D, int32_t n, double eps, hipStream_t st) {
+void launch_eig_list_f32(const Dev& D, int32_t n, double eps, int mirror, hipStream_t st) {
   if (n <= 0) return;
-  k_eig_list<float><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps);
+  k_eig_list<float><<<(n + kBlock - 1) / kBlock, kBlock, 0, st>>>(D, n, eps, mirror);
 }
 
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st) {

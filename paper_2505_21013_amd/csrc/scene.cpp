@@ -347,6 +347,7 @@ void Scene::set_params(const ppn_params& p) {
     fail("bad Newton / line-search parameters");
   if (!(p.armijo_c > 0.0 && p.armijo_c < 1.0)) fail("armijo_c must be in (0, 1)");
   if (!(p.k_dirichlet >= 0.0)) fail("k_dirichlet must be >= 0");
+  if (p.eig_mirror != 0 && p.eig_mirror != 1) fail("eig_mirror must be 0 or 1");
   prm_ = p;
   D_.k_dir = p.k_dirichlet;
 }
@@ -364,16 +365,16 @@ void Scene::evaluate_at_current_x() {
 
 void Scene::eig_all() {
   if (precision_ == PPN_MIXED)
-    launch_eig_all_f32(D_, prm_.eps_clamp, st_);
+    launch_eig_all_f32(D_, prm_.eps_clamp, prm_.eig_mirror, st_);
   else
-    launch_eig_all(D_, prm_.eps_clamp, st_);
+    launch_eig_all(D_, prm_.eps_clamp, prm_.eig_mirror, st_);
 }
 
 void Scene::eig_list(int32_t n) {
   if (precision_ == PPN_MIXED)
-    launch_eig_list_f32(D_, n, prm_.eps_clamp, st_);
+    launch_eig_list_f32(D_, n, prm_.eps_clamp, prm_.eig_mirror, st_);
   else
-    launch_eig_list(D_, n, prm_.eps_clamp, st_);
+    launch_eig_list(D_, n, prm_.eps_clamp, prm_.eig_mirror, st_);
 }
 
 void Scene::project_all() {

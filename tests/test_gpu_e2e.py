@@ -17,11 +17,15 @@ from helpers import gpu_scene
 pytestmark = pytest.mark.gpu
 
 
-def _run_pair(sc, mode, n_steps, trace=True):
+def _run_pair(sc, mode, n_steps, trace=True, **variant):
+    """Both sides on the same scene; ``variant`` holds parameters shared by the
+    oracle's Params and the library's ppn_params (alpha, beta, pdn_countdown,
+    eig_mirror)."""
     orc_x, orc_stats = [], []
-    stp, ost = oracle.run_scene(sc, mode, n_steps=n_steps, trace=trace,
+    prm = oracle.Params(stop_mode=sc.stop_mode, stop_tol=sc.stop_tol, **variant)
+    stp, ost = oracle.run_scene(sc, mode, n_steps=n_steps, params=prm, trace=trace,
                                 callback=lambda n, s, st: orc_x.append(s.x.copy()))
-    gpu = gpu_scene(sc, trace=trace)
+    gpu = gpu_scene(sc, trace=trace, **{k: int(v) if isinstance(v, bool) else v for k, v in variant.items()})
     gx, gtr = [], []
 
     def cb(n, s, st):
@@ -32,15 +36,20 @@ def _run_pair(sc, mode, n_steps, trace=True):
     return ost, orc_x, gst, gx, gtr
 
 
-def _compare(sc, mode, n_steps):
-    ost, ox, gst, gx, gtr = _run_pair(sc, mode, n_steps)
+def _compare(sc, mode, n_steps, allow_unconverged=False, **variant):
+    """With allow_unconverged a step may end at the Newton-iteration cap, as
+    long as both sides do."""
+    ost, ox, gst, gx, gtr = _run_pair(sc, mode, n_steps, **variant)
     diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
     for n in range(n_steps):
         o, g = ost[n], gst[n]
         tag = f"{sc.name} {mode} step {n + 1}"
         o_conv, o_fail, o_ni, o_proj, o_rounds = o.converged, o.ls_fail, o.newton_iters, o.projected, o.inner_rounds
         o_ind, o_safe, o_res, o_res0 = o.indefinite_solves, o.safety_events, o.res_l2, o.res0_l2
-        assert g["status"] == "PPN_OK" and o_conv and not o_fail, (tag, g["status"])
+        if allow_unconverged:
+            assert (g["status"] == "PPN_OK") == o_conv and not o_fail, (tag, g["status"])
+        else:
+            assert g["status"] == "PPN_OK" and o_conv and not o_fail, (tag, g["status"])
         assert g["newton_iters"] == o_ni, (tag, g["newton_iters"], o_ni)
         assert g["projected"] == o_proj, (tag, g["projected"], o_proj)
         assert g["inner_rounds"] == o_rounds, (tag, g["inner_rounds"], o_rounds)

@@ -215,6 +215,34 @@ def test_P7_P8_projection_properties():
     assert np.max(np.abs(project_to_pd(S, eps) - S)) <= 1e-13 * np.linalg.norm(S, axis=(1, 2)).max()
 
 
+def test_P7m_mirroring_is_the_matrix_absolute_value():
+    """Mirroring replaces every eigenvalue by max(|lambda|, eps).  Where every
+    |lambda| >= eps that is the matrix absolute value |H| = (H^2)^(1/2), which
+    scipy computes by a Schur-based square root (no eigendecomposition of H);
+    on prescribed spectra it is Q diag(max(|d|, eps)) Q^T built by hand."""
+    import scipy.linalg
+    rng = np.random.default_rng(81)
+    for _ in range(5):
+        Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+        d = rng.uniform(0.5, 3.0, 12) * rng.choice([-1.0, 1.0], 12)
+        H = (Q * d) @ Q.T
+        H = 0.5 * (H + H.T)
+        Hm = project_to_pd(H, 1e-8, mirror=True)
+        ref = np.real(scipy.linalg.sqrtm(H @ H))
+        assert np.max(np.abs(Hm - ref)) <= 1e-9
+        assert np.max(np.abs(Hm - (Q * np.abs(d)) @ Q.T)) <= 1e-12
+    # tiny and zero eigenvalues are lifted to eps, as with clamping
+    Q, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+    d = np.array([-2.0, -1e-12, 0.0, 3e-9, 1.0, 5.0])
+    H = (Q * d) @ Q.T
+    want = (Q * np.maximum(np.abs(d), 1e-8)) @ Q.T
+    assert np.max(np.abs(project_to_pd(0.5 * (H + H.T), 1e-8, mirror=True) - want)) <= 1e-13
+    # mirroring and clamping agree on matrices with no eigenvalue below eps
+    S = (Q * np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])) @ Q.T
+    S = 0.5 * (S + S.T)
+    assert np.max(np.abs(project_to_pd(S, 1e-8, mirror=True) - project_to_pd(S, 1e-8))) <= 1e-13
+
+
 # ---------------------------------------------------------------- P9: the paper's worked example
 def _paper_example():
     mats = {}
