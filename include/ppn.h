@@ -292,6 +292,8 @@ typedef struct {
   int64_t admissions;      /* scene loads into device memory */
   int64_t evictions;       /* scenes moved out to make room */
   int32_t resident_scenes, n_scenes, n_workers, pending;
+  int64_t pcg_batches;         /* shared-launch PCG chunks run (batching on) */
+  int64_t pcg_batched_solves;  /* solves carried by them */
 } ppn_engine_info;
 
 /* Create an engine on the current HIP device.  mem_budget_bytes <= 0 means 90%
@@ -320,6 +322,14 @@ ppn_status ppn_engine_wait(ppn_engine* e, int64_t request_id, ppn_status* step_s
  * requests are done (waits for them). */
 ppn_status ppn_engine_get_state(ppn_engine* e, int32_t scene_id, double* x_out, double* v_out);
 ppn_status ppn_engine_get_info(ppn_engine* e, ppn_engine_info* out);
+/* Batched PCG (enable = 1): the solves of scenes being stepped at the same
+ * time run in shared launches (one matrix-product and one update launch per
+ * iteration for all of them, each workgroup working for one scene), which
+ * removes the per-scene launch latency of small scenes.  Solves join and
+ * leave the running batch at chunk boundaries (every 16 iterations).
+ * Results are unchanged bit for bit.  Off by default.  PPN_ERR_STATE unless
+ * the engine is idle. */
+ppn_status ppn_engine_set_pcg_batching(ppn_engine* e, int32_t enable);
 
 #ifdef __cplusplus
 }

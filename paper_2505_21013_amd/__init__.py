@@ -365,6 +365,9 @@ class Engine:
         _check(_abi.lib().ppn_engine_get_state(self._h, int(scene_id), _d(x), _d(v)))
         return x, v
 
+    def ppn_engine_set_pcg_batching(self, enable=True):
+        _check(_abi.lib().ppn_engine_set_pcg_batching(self._h, int(bool(enable))))
+
     def ppn_engine_get_info(self):
         i = ppn_engine_info()
         _check(_abi.lib().ppn_engine_get_info(self._h, C.byref(i)))

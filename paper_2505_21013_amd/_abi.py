@@ -58,7 +58,8 @@ class ppn_scene_desc(C.Structure):
 class ppn_engine_info(C.Structure):
     _fields_ = [("budget_bytes", C.c_int64), ("resident_bytes", C.c_int64), ("admissions", C.c_int64),
                 ("evictions", C.c_int64), ("resident_scenes", C.c_int32), ("n_scenes", C.c_int32),
-                ("n_workers", C.c_int32), ("pending", C.c_int32)]
+                ("n_workers", C.c_int32), ("pending", C.c_int32), ("pcg_batches", C.c_int64),
+                ("pcg_batched_solves", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -108,6 +109,7 @@ SIGNATURES = {
     "ppn_engine_wait": (C.c_int, [P, C.c_int64, C.POINTER(C.c_int), C.POINTER(ppn_step_stats), dp, dp]),
     "ppn_engine_get_state": (C.c_int, [P, C.c_int32, dp, dp]),
     "ppn_engine_get_info": (C.c_int, [P, C.POINTER(ppn_engine_info)]),
+    "ppn_engine_set_pcg_batching": (C.c_int, [P, C.c_int32]),
 }
 
 _lib = None

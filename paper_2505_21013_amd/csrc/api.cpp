@@ -414,6 +414,14 @@ ppn_status ppn_engine_get_state(ppn_engine* e, int32_t scene_id, double* x_out, 
   });
 }
 
+ppn_status ppn_engine_set_pcg_batching(ppn_engine* e, int32_t enable) {
+  ENGINE(e);
+  return guarded(nullptr, [&]() -> ppn_status {
+    EG.set_pcg_batching(enable != 0);
+    return PPN_OK;
+  });
+}
+
 ppn_status ppn_engine_get_info(ppn_engine* e, ppn_engine_info* out) {
   ENGINE(e);
   if (!out) {

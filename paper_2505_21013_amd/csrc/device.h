@@ -156,6 +156,32 @@ void launch_pcg_iter(const Dev& D, const PcgVec<double>& V, int j, double tol2, 
 void launch_pcg_iter(const Dev& D, const PcgVec<float>& V, int j, double tol2, int maxit,
                      hipStream_t st, hipEvent_t ev_spmv_start = nullptr,
                      hipEvent_t ev_spmv_stop = nullptr);
+// One PCG solve of a batch (see the batched launchers below).
+template <typename M>
+struct PcgJob {
+  Dev D;
+  PcgVec<M> V;
+  const double* src;  // right-hand side = sign * src
+  double sign;
+  double tol2;        // rtol^2
+  int32_t maxit;
+  int32_t wg0;        // first global workgroup of this job; jobs sorted by wg0
+  int32_t j0;         // batch iteration at which this job's solve started
+  int32_t pad;
+};
+// Batched solves: n jobs, total_wg = sum of their Gp; every launch covers all
+// jobs and a finished job's workgroups return at once.  Iteration j of the
+// batch is iteration j - j0 of each job.
+void launch_pcg_batch_init(const PcgJob<double>* jobs, int n, int total_wg, hipStream_t st);
+void launch_pcg_batch_init(const PcgJob<float>* jobs, int n, int total_wg, hipStream_t st);
+// any_first: some job starts at this iteration (its first product is a
+// separate instance, launched only then).
+void launch_pcg_batch_iter(const PcgJob<double>* jobs, int n, int total_wg, int j, bool any_first,
+                           hipStream_t st);
+void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j, bool any_first,
+                           hipStream_t st);
+void launch_pcg_batch_gather(const PcgJob<double>* jobs, int n, PcgState* out, hipStream_t st);
+void launch_pcg_batch_gather(const PcgJob<float>* jobs, int n, PcgState* out, hipStream_t st);
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // FP32 copy of the sliced-ELL values, entries paired for 8-byte loads.
 void launch_sell_to_f32(const double* src, float* dst, int64_t n_slots, hipStream_t st);

@@ -34,6 +34,17 @@ int32_t Engine::n_scenes() {
   return int32_t(slots_.size());
 }
 
+void Engine::set_pcg_batching(bool on) {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto& s : slots_)
+    if (s->busy) throw HipError{"set_pcg_batching needs an idle engine", PPN_ERR_STATE};
+  if (!pending_.empty()) throw HipError{"set_pcg_batching needs an idle engine", PPN_ERR_STATE};
+  if (on && !batcher_) batcher_ = std::make_unique<PcgBatcher>(device_);
+  for (auto& s : slots_)
+    if (s->dev) s->dev->set_batcher(on ? batcher_.get() : nullptr);
+  if (!on) batcher_.reset();
+}
+
 int64_t Engine::footprint(int32_t scene) {
   std::lock_guard<std::mutex> lk(mu_);
   if (scene < 0 || scene >= int32_t(slots_.size())) fail_arg("unknown scene id");
@@ -167,6 +178,7 @@ std::unique_ptr<Scene> Engine::build(Slot& s) {
   sc->load_mesh(std::move(t), s.X.data(), s.tets.data(), nullptr);
   sc->set_material(s.rho, s.E.data(), s.nu.data(), s.E.size() > 1);
   sc->set_state(s.x.data(), s.v.data());
+  sc->set_batcher(batcher_.get());
   return sc;
 }
 
@@ -270,6 +282,8 @@ void Engine::info(ppn_engine_info* out) {
   out->n_scenes = int32_t(slots_.size());
   out->n_workers = int32_t(workers_.size());
   out->pending = int32_t(pending_.size());
+  out->pcg_batches = batcher_ ? batcher_->batches() : 0;
+  out->pcg_batched_solves = batcher_ ? batcher_->solves() : 0;
 }
 
 }  // namespace ppn

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/ppn.h"
+#include "pcg_batch.h"
 #include "scene.h"
 #include "topology.h"
 
@@ -41,6 +42,8 @@ class Engine {
   void info(ppn_engine_info* out);
   int32_t n_scenes();
   int64_t footprint(int32_t scene);
+  // Batched PCG solves across scenes on or off; only while no request is pending or running.
+  void set_pcg_batching(bool on);
 
  private:
   using Clock = std::chrono::steady_clock;
@@ -81,6 +84,7 @@ class Engine {
   std::unique_ptr<Scene> build(Slot& s);
 
   int device_;
+  std::unique_ptr<PcgBatcher> batcher_;  // declared before the slots: outlives their scenes
   int64_t budget_;
   int64_t resident_bytes_ = 0;
   int64_t admissions_ = 0, evictions_ = 0;

@@ -46,8 +46,9 @@ namespace ppn {
 
 constexpr int kPcgBlock = 256;  // threads per PCG workgroup: 4 groups of 64 rows
 
-__device__ inline void pcg_finish(const Dev& D, int ind, int iters) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+// The decision is recorded by the scene's logical workgroup 0.
+__device__ inline void pcg_finish(const Dev& D, int w, int ind, int iters) {
+  if (w == 0 && threadIdx.x == 0) {
     D.pcg->ind = ind;
     D.pcg->iters = iters;
     D.pcg->done = 1;
@@ -56,12 +57,14 @@ __device__ inline void pcg_finish(const Dev& D, int ind, int iters) {
 
 // r = sign * src, x = 0, z = P^-1 r into zd[0]; partials of r^T r, r^T z and
 // the count of diagonal blocks failing Sylvester's criterion.
+// The bodies below take the scene's logical workgroup index w (0 .. Gp-1):
+// the single-scene kernels derive it from the hardware index, the batched
+// kernels from the job table.
 template <typename M>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, const double* src,
-                                                         double sign) {
+__device__ __forceinline__ void pcg_init_body(const Dev& D, const PcgVec<M>& V, const double* src,
+                                              double sign, int w) {
   __shared__ double lds[16];
   const int Gp = D.Gp, N = D.N;
-  const int w = logical_wg(Gp);
   const int i = w * kPcgBlock + threadIdx.x;
   double rr = 0.0, rz = 0.0, bad = 0.0;
   if (i < N) {
@@ -91,11 +94,17 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, cons
     D.part[kPartRZ0 * Gp + w] = rz;
     D.part[kPartSpd * Gp + w] = bad;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (w == 0 && threadIdx.x == 0) {
     D.pcg->done = 0;
     D.pcg->ind = 0;
     D.pcg->iters = 0;
   }
+}
+
+template <typename M>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, const double* src,
+                                                         double sign) {
+  pcg_init_body<M>(D, V, src, sign, logical_wg(D.Gp));
 }
 
 // q_i = sum over the row's slots of B d_col, d read from a plain [N][3] vector (FP64).
@@ -185,9 +194,13 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
 // The streaming loop does not depend on this iteration's scalars: the partial
 // sums that decide beta and the stop test are loaded first, the product runs,
 // and only then are the partials combined (their load latency hides under the loop).
+// kFirst: the first product of a solve.  It stays a compile-time constant in
+// the batched kernels too, so that they compile to the same arithmetic as the
+// single-scene kernels (a runtime flag changes which products the compiler
+// fuses into FMAs, and with it the last bits).
 template <typename M, bool kFirst>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int j, double tol2,
-                                                        int maxit) {
+__device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, int j, double tol2,
+                                              int maxit, int w) {
   __shared__ double lds[16];
   if (D.pcg->done) return;
   const int Gp = D.Gp;
@@ -201,7 +214,6 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int 
     sb += pb[k];
     if (kFirst) sc += D.part[kPartSpd * Gp + k];
   }
-  const int w = logical_wg(Gp);
   const int i = w * kPcgBlock + threadIdx.x;
   const int g = i / kSell, l = i % kSell;
   M qz[3] = {0, 0, 0}, qd[3] = {0, 0, 0};
@@ -222,19 +234,19 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int 
   const double bad = ((lds[8] + lds[9]) + lds[10]) + lds[11];
   double beta = 0.0;
   if (kFirst) {
-    if (bad > 0.0) { pcg_finish(D, 1, 0); return; }
-    if (rr == 0.0) { pcg_finish(D, 0, 0); return; }
-    if (rz <= 0.0) { pcg_finish(D, 1, 0); return; }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bad > 0.0) { pcg_finish(D, w, 1, 0); return; }
+    if (rr == 0.0) { pcg_finish(D, w, 0, 0); return; }
+    if (rz <= 0.0) { pcg_finish(D, w, 1, 0); return; }
+    if (w == 0 && threadIdx.x == 0) {
       D.pcg->rr0 = rr;
       D.pcg->rz[0] = rz;
     }
   } else {
-    if (rr <= tol2 * D.pcg->rr0) { pcg_finish(D, 0, j); return; }
-    if (rz <= 0.0) { pcg_finish(D, 1, j); return; }
-    if (j >= maxit) { pcg_finish(D, 0, j); return; }
+    if (rr <= tol2 * D.pcg->rr0) { pcg_finish(D, w, 0, j); return; }
+    if (rz <= 0.0) { pcg_finish(D, w, 1, j); return; }
+    if (j >= maxit) { pcg_finish(D, w, 0, j); return; }
     beta = rz / D.pcg->rz[(j - 1) & 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) D.pcg->rz[j & 1] = rz;
+    if (w == 0 && threadIdx.x == 0) D.pcg->rz[j & 1] = rz;
   }
   double kap = 0.0;
   if (i < D.N) {
@@ -263,19 +275,24 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int 
   if (threadIdx.x == 0) D.part[kPartKappa * Gp + w] = kap;
 }
 
+template <typename M, bool kFirst>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int j, double tol2,
+                                                        int maxit) {
+  pcg_spmv_body<M, kFirst>(D, V, j, tol2, maxit, logical_wg(D.Gp));
+}
+
 // The row's inputs are loaded before the d^T q partials are combined, so both
 // latencies overlap.  The workgroup's 256 vertices own a contiguous run of
 // 768 values of each [N][3] vector: q, r and x are moved between HBM and LDS
 // with unit-stride loads and stores and read per vertex from LDS, instead of
 // three 24-byte-strided accesses per vector and lane.
 template <typename M>
-__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, int j) {
+__device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V, int j, int w) {
   __shared__ double lds[16];
   __shared__ double sq[3 * kPcgBlock], sr[3 * kPcgBlock], sx[3 * kPcgBlock];
   if (D.pcg->done) return;
   const int Gp = D.Gp, N = D.N;
   double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(N));
-  const int w = logical_wg(Gp);
   const int t = threadIdx.x;
   const int i = w * kPcgBlock + t;
   const int64_t f0 = int64_t(w) * (3 * kPcgBlock);  // first vector value of the workgroup
@@ -297,7 +314,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, in
     for (int k = 0; k < 9; ++k) P[k] = double(__builtin_nontemporal_load(V.pinv + k * N + i));
   }
   const double kap = reduce_partials(D.part + kPartKappa * Gp, Gp, lds);  // synchronises
-  if (kap <= 0.0) { pcg_finish(D, 1, j + 1); return; }
+  if (kap <= 0.0) { pcg_finish(D, w, 1, j + 1); return; }
   const double alpha = D.pcg->rz[j & 1] / kap;
   double rr = 0.0, rzn = 0.0;
   if (i < N) {
@@ -330,6 +347,11 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, in
     D.part[kPartRR * Gp + w] = rr;
     D.part[((j & 1) ? kPartRZ0 : kPartRZ1) * Gp + w] = rzn;
   }
+}
+
+template <typename M>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, int j) {
+  pcg_update_body<M>(D, V, j, logical_wg(D.Gp));
 }
 
 template <typename T>
@@ -481,6 +503,95 @@ void launch_refine_add(const Dev& D, const double* e, hipStream_t st) {
 }
 void launch_refine_residual(const Dev& D, hipStream_t st) {
   k_refine_residual<<<D.Gp, kPcgBlock, 0, st>>>(D);
+}
+
+// ---- batched solves: one launch over the workgroups of many scenes ----
+// Job k owns the global workgroups [wg0_k, wg0_k + Gp_k); each workgroup finds
+// its job by binary search and runs the scene's body with its local index and
+// the job's own iteration number (jobs join a running batch), so every scene
+// computes exactly what it computes alone.
+template <typename M>
+__device__ __forceinline__ const PcgJob<M>& find_job(const PcgJob<M>* __restrict__ jobs, int n,
+                                                    int& w) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg0 <= b) lo = mid; else hi = mid - 1;
+  }
+  w = b - jobs[lo].wg0;
+  return jobs[lo];
+}
+
+template <typename M>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_init_batch(const PcgJob<M>* __restrict__ jobs, int n) {
+  int w;
+  const PcgJob<M>& J = find_job(jobs, n, w);
+  pcg_init_body<M>(J.D, J.V, J.src, J.sign, w);
+}
+
+// Iteration jg of the batch is iteration jg - j0 of each job's own solve.  The
+// kFirst instance serves the jobs at their first iteration, the other the rest.
+template <typename M, bool kFirst>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv_batch(const PcgJob<M>* __restrict__ jobs, int n,
+                                                              int jg) {
+  int w;
+  const PcgJob<M>& J = find_job(jobs, n, w);
+  const int j = jg - J.j0;
+  if ((j == 0) != kFirst) return;
+  pcg_spmv_body<M, kFirst>(J.D, J.V, j, J.tol2, J.maxit, w);
+}
+
+template <typename M>
+__global__ __launch_bounds__(kPcgBlock) void k_pcg_update_batch(const PcgJob<M>* __restrict__ jobs, int n,
+                                                                int jg) {
+  int w;
+  const PcgJob<M>& J = find_job(jobs, n, w);
+  pcg_update_body<M>(J.D, J.V, jg - J.j0, w);
+}
+
+// out[k] = job k's PcgState (one read-back for the whole batch).
+template <typename M>
+__global__ void k_pcg_gather_state(const PcgJob<M>* __restrict__ jobs, int n, PcgState* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = *jobs[k].D.pcg;
+}
+
+template <typename M>
+static void batch_init(const PcgJob<M>* jobs, int n, int total_wg, hipStream_t st) {
+  k_pcg_init_batch<M><<<total_wg, kPcgBlock, 0, st>>>(jobs, n);
+}
+template <typename M>
+static void batch_iter(const PcgJob<M>* jobs, int n, int total_wg, int j, bool any_first,
+                       hipStream_t st) {
+  if (any_first) k_pcg_spmv_batch<M, true><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+  k_pcg_spmv_batch<M, false><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+  k_pcg_update_batch<M><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+}
+template <typename M>
+static void batch_gather(const PcgJob<M>* jobs, int n, PcgState* out, hipStream_t st) {
+  k_pcg_gather_state<M><<<(n + 63) / 64, 64, 0, st>>>(jobs, n, out);
+}
+
+void launch_pcg_batch_init(const PcgJob<double>* jobs, int n, int total_wg, hipStream_t st) {
+  batch_init(jobs, n, total_wg, st);
+}
+void launch_pcg_batch_init(const PcgJob<float>* jobs, int n, int total_wg, hipStream_t st) {
+  batch_init(jobs, n, total_wg, st);
+}
+void launch_pcg_batch_iter(const PcgJob<double>* jobs, int n, int total_wg, int j, bool any_first,
+                           hipStream_t st) {
+  batch_iter(jobs, n, total_wg, j, any_first, st);
+}
+void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j, bool any_first,
+                           hipStream_t st) {
+  batch_iter(jobs, n, total_wg, j, any_first, st);
+}
+void launch_pcg_batch_gather(const PcgJob<double>* jobs, int n, PcgState* out, hipStream_t st) {
+  batch_gather(jobs, n, out, st);
+}
+void launch_pcg_batch_gather(const PcgJob<float>* jobs, int n, PcgState* out, hipStream_t st) {
+  batch_gather(jobs, n, out, st);
 }
 
 }  // namespace ppn

@@ -438,6 +438,11 @@ void Scene::project_mask(const uint8_t* mask) {
 template <typename T>
 void Scene::run_pcg(const PcgVec<T>& V, const double* src, double sign, double rtol, int maxit,
                     int32_t& ind, int32_t& iters) {
+  if (batcher_) {
+    sync();  // the batcher's stream reads what this stream wrote
+    batcher_->solve(D_, V, src, sign, rtol, maxit, ind, iters);
+    return;
+  }
   launch_pcg_init(D_, V, src, sign, st_);
   LAUNCHCHK();
   const double tol2 = rtol * rtol;

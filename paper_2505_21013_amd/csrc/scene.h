@@ -8,6 +8,7 @@
 
 #include "../../include/ppn.h"
 #include "device.h"
+#include "pcg_batch.h"
 #include "topology.h"
 
 namespace ppn {
@@ -56,6 +57,8 @@ class Scene {
   void get_state(double* x, double* v);
   void set_state(const double* x, const double* v);
 
+  // Hand PCG solves to a batcher shared with other scenes (nullptr: solve alone).
+  void set_batcher(PcgBatcher* b) { batcher_ = b; }
   bool loaded() const { return D_.N > 0; }
   const Dev& dev() const { return D_; }
   const Topology& topo() const { return topo_; }
@@ -92,6 +95,7 @@ class Scene {
   hipStream_t st_;
   bool own_stream_;
   int precision_;
+  PcgBatcher* batcher_ = nullptr;
   Dev D_;
   Topology topo_;
   std::vector<void*> allocs_;

@@ -2,7 +2,8 @@
 
 * Each result is bit-identical alone and in the mix: the same requests run one
   scene at a time on one worker, all at once on several workers (their kernels
-  overlapping on the device), and through the single-scene API.
+  overlapping on the device), with their PCG solves batched into shared
+  launches, and through the single-scene API.
 * Admission by footprint: with a budget for two scenes, four scenes take turns
   in device memory (evictions keep the state on the host) with unchanged results.
 * Against the FP64 oracle: rotated blocks of the batched workload, stepped in the
@@ -70,6 +71,28 @@ def test_engine_results_identical_alone_and_in_mix():
         x, v = g.ppn_get_state()
         g.close()
         assert np.array_equal(x, st_mix[i][0]) and np.array_equal(v, st_mix[i][1])
+
+
+@pytest.mark.parametrize("precision", [PPN_FP64, PPN_MIXED])
+def test_engine_pcg_batching_changes_nothing(precision):
+    """Solves of scenes stepped at the same time share launches; every scene's
+    bits stay those of its unbatched run."""
+    scenes = _small_scenes(6)
+    with Engine(n_workers=1) as e1:
+        ids1 = [e1.add_scene(sc, precision=precision) for sc in scenes]
+        alone, st_alone = _run(e1, scenes, ids1, 3, interleave=False)
+    with Engine(n_workers=6) as eb:
+        eb.ppn_engine_set_pcg_batching(True)
+        idsb = [eb.add_scene(sc, precision=precision) for sc in scenes]
+        mix, st_mix = _run(eb, scenes, idsb, 3, interleave=True)
+        info = eb.ppn_engine_get_info()
+    n_solves = sum(s["solves"] for st in mix.values() for s in st)
+    assert info["pcg_batches"] > 0 and info["pcg_batched_solves"] >= n_solves > 0, info
+    for i in range(len(scenes)):
+        for n, (a, b) in enumerate(zip(alone[i], mix[i])):
+            diff = {k: (a[k], b[k]) for k in KEYS if a[k] != b[k]}
+            assert not diff, (scenes[i].name, n + 1, diff)
+        assert np.array_equal(st_alone[i][0], st_mix[i][0]) and np.array_equal(st_alone[i][1], st_mix[i][1])
 
 
 def test_engine_footprint_is_device_bytes():
