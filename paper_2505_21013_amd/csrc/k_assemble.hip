@@ -57,47 +57,7 @@ __device__ inline void store_diag(const Dev& D, int i, const double hd[6]) {
   D.spd_ok[i] = ok ? 1 : 0;
 }
 
-// Vertex pass of the full assembly: gradient, |g_i|_inf, diagonal block,
-// block-Jacobi inverse, and partial |g|_2^2 and |g|_inf per workgroup.
-__global__ __launch_bounds__(kBlock) void k_assemble_vertex(Dev D) {
-  __shared__ double lds[16];
-  const int G = D.G;
-  const int w = logical_wg(G);
-  const int i0 = w * D.rows_per_wg, i1 = min(D.N, i0 + D.rows_per_wg);
-  const double ih2 = 1.0 / (D.h * D.h);
-  double g2 = 0.0, gm = 0.0;
-  for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = D.vptr[i]; k < D.vptr[i + 1]; ++k) {
-      const double* sl = D.vslots + size_t(k) * 9;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) s[c] += sl[c];
-    }
-    const int di = D.dir_idx[i];
-    double gi[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double xi = D.x[3 * i + c];
-      double t = s[c] + D.mass[i] * ih2 * (xi - D.xhat[3 * i + c]);
-      if (di >= 0) t += D.k_dir * (xi - D.xbar[3 * di + c]);
-      gi[c] = t;
-      D.g[3 * i + c] = t;
-    }
-    const double r = fmax(fabs(gi[0]), fmax(fabs(gi[1]), fabs(gi[2])));
-    D.rinf[i] = r;
-    g2 += gi[0] * gi[0] + gi[1] * gi[1] + gi[2] * gi[2];
-    gm = fmax(gm, r);
-    store_diag(D, i, s + 3);
-  }
-  g2 = block_sum(g2, lds);
-  gm = block_max(gm, lds);
-  if (threadIdx.x == 0) {
-    D.part[kPartG2 * G + w] = g2;
-    D.part[kPartGmax * G + w] = gm;
-  }
-}
-
-// Edge pass: off-diagonal block (lo, hi) and its transpose (hi, lo).
+// One edge block (lo, hi) and its transpose (hi, lo) from the edge's slots.
 __device__ inline void gather_edge(const Dev& D, int k) {
   double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = D.eptr[k]; t < D.eptr[k + 1]; ++t) {
@@ -116,6 +76,68 @@ __device__ inline void gather_edge(const Dev& D, int k) {
     }
 }
 
+// Vertex pass of the full assembly: gradient, |g_i|_inf, diagonal block,
+// block-Jacobi inverse, and partial |g|_2^2 and |g|_inf per workgroup.
+//
+// The slot sums are component-parallel: thread (v, c) of a chunk of
+// kVChunk vertices sums component c of vertex v's slots, so the threads of a
+// wavefront read consecutive doubles of the contiguous slot range of their
+// vertices (instead of one lane streaming a vertex's ~1.7 KB range alone);
+// each component is summed in ascending slot order as before.  The sums meet
+// in LDS and one thread per vertex finishes it.
+constexpr int kVChunk = kBlock / 9;  // 28 vertices (252 threads) per chunk
+
+__global__ __launch_bounds__(kBlock) void k_assemble_vertex(Dev D) {
+  __shared__ double lds[16];
+  __shared__ double sv[kVChunk][9];
+  const int G = D.G;
+  const int w = logical_wg(G);
+  const int i0 = w * D.rows_per_wg, i1 = min(D.N, i0 + D.rows_per_wg);
+  const double ih2 = 1.0 / (D.h * D.h);
+  const int t = threadIdx.x, vl = t / 9, c = t % 9;
+  double g2 = 0.0, gm = 0.0;
+  for (int base = i0; base < i1; base += kVChunk) {
+    const int i = base + vl;
+    if (vl < kVChunk && i < i1) {
+      double s = 0.0;
+#pragma unroll 8
+      for (int k = D.vptr[i]; k < D.vptr[i + 1]; ++k) s += D.vslots[size_t(k) * 9 + c];
+      sv[vl][c] = s;
+    }
+    __syncthreads();
+    if (t < kVChunk && base + t < i1) {
+      const int iv = base + t;
+      const double* sl = sv[t];
+      const int di = D.dir_idx[iv];
+      double gi[3];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const double xi = D.x[3 * iv + cc];
+        double tt = sl[cc] + D.mass[iv] * ih2 * (xi - D.xhat[3 * iv + cc]);
+        if (di >= 0) tt += D.k_dir * (xi - D.xbar[3 * di + cc]);
+        gi[cc] = tt;
+        D.g[3 * iv + cc] = tt;
+      }
+      const double r = fmax(fabs(gi[0]), fmax(fabs(gi[1]), fabs(gi[2])));
+      D.rinf[iv] = r;
+      g2 += gi[0] * gi[0] + gi[1] * gi[1] + gi[2] * gi[2];
+      gm = fmax(gm, r);
+      double hd[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) hd[q] = sl[3 + q];
+      store_diag(D, iv, hd);
+    }
+    __syncthreads();
+  }
+  g2 = block_sum(g2, lds);
+  gm = block_max(gm, lds);
+  if (threadIdx.x == 0) {
+    D.part[kPartG2 * G + w] = g2;
+    D.part[kPartGmax * G + w] = gm;
+  }
+}
+
+// Edge pass: off-diagonal block (lo, hi) and its transpose (hi, lo).
 __global__ __launch_bounds__(kBlock) void k_assemble_edge(Dev D) {
   const int k = blockIdx.x * kBlock + threadIdx.x;
   if (k >= D.E) return;
