@@ -44,11 +44,13 @@ typedef struct ppn_scene ppn_scene; /* opaque, library-owned */
 typedef enum { PPN_PN = 0, PPN_PDN = 1, PPN_PPN = 2 } ppn_mode;
 
 /* Arithmetic of the hot path.  PPN_FP64: everything in FP64.  PPN_MIXED:
- * eigensolves and PCG (matrix, vectors, matrix product) in FP32 with FP32
- * accumulation; element energies, gradients, Hessian assembly, dot products,
- * the Newton residual, the line-search energy sum and the iterative-refinement
- * residual of each linear solve stay FP64 (the FP32 solve is repeated on the
- * FP64 residual until that meets pcg_rtol). */
+ * eigensolves in FP32; inside PCG the assembled matrix and block-Jacobi
+ * inverse are stored in FP32 and the matrix product is formed and accumulated
+ * in FP32, while the CG vectors, their recurrences and all dot products stay
+ * FP64; element energies, gradients, Hessian assembly, the Newton residual,
+ * the line-search energy sum and the iterative-refinement residual of each
+ * linear solve stay FP64 (the solve is repeated on the FP64 residual until
+ * that meets pcg_rtol). */
 typedef enum { PPN_FP64 = 0, PPN_MIXED = 1 } ppn_precision;
 
 /* Newton stopping rule.  VEL (Sec. 5.1): stop once |dx|_inf / h < stop_tol
@@ -113,8 +115,8 @@ typedef struct {
   double ms_spmv;            /* summed duration of the sampled PCG matrix-product launches,
                                 measured with HIP events when profiling is on (else 0) [ms] */
   int64_t n_spmv;            /* sampled launches summed in ms_spmv */
-  int32_t refine_rounds;     /* PPN_MIXED: FP32 inner solves (each followed by an FP64
-                                residual); 0 in PPN_FP64 */
+  int32_t refine_rounds;     /* PPN_MIXED: PCG runs with the FP32 matrix (each followed
+                                by an FP64 residual); 0 in PPN_FP64 */
   int32_t reserved1;
 } ppn_step_stats;
 

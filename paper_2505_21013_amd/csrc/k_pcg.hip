@@ -408,7 +408,7 @@ void launch_spmv_plain(const Dev& D, const double* d, double* q, hipStream_t st)
   k_spmv_plain<<<D.Gp, kPcgBlock, 0, st>>>(D, d, q);
 }
 
-// ---- mixed precision: FP32 inner solves refined against the FP64 system ----
+// ---- mixed precision: solves with the FP32 matrix refined against the FP64 system ----
 
 // dst = float(src) over n values.
 __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ src,
