@@ -230,7 +230,9 @@ def run_batch(a):
             out[key] = {"workers": workers, "pcg_batching": batched, "value": len(reqs) / el,
                         "elapsed_s": el, "all_converged": ok,
                         "newton_iters": sum(r["newton_iters"] for r in res),
-                        "pcg_iters": sum(r["pcg_iters"] for r in res)}
+                        "pcg_iters": sum(r["pcg_iters"] for r in res),
+                        "mean_step_ms": sum(r["ms_total"] for r in res) / len(res),
+                        "mean_step_pcg_ms": sum(r["ms_pcg"] for r in res) / len(res)}
             if batched:
                 out[key]["pcg_chunks"] = info["pcg_batches"]
                 out[key]["pcg_solves"] = info["pcg_batched_solves"]
