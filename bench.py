@@ -147,8 +147,9 @@ def composite_roofline(R, precision, info, K):
       element evaluation + assembly, per Newton iteration: 1592 B per tet
         (152 B of element data read, 720 B of slots written, slots read back
         once by the vertex and edge passes), 261 B per vertex, 148 B per edge;
-      PCG iteration: the matrix product (spmv_bytes) + the update (240 B per
-        vertex; 204 B with the FP32 block-Jacobi inverse);
+      PCG iteration: the matrix product (spmv_bytes) + the update (216 B per
+        vertex: q, d, r, x and the 6-entry symmetric block-Jacobi inverse read,
+        x, r and z written; 192 B with the FP32 inverse);
       line-search pass (four step sizes): 112 B per tet + 84 B per vertex;
       eigen-projection: 45.6 kflop (measured executed flops of the 9x9 Jacobi)."""
     N, T, NB = info["n_verts"], info["n_tets"], info["n_blocks"]
@@ -156,7 +157,7 @@ def composite_roofline(R, precision, info, K):
     tot = R["tot"]
     fp32 = precision == "mixed"
     bw = HBM_PEAK_GBS * 1e9
-    pcg = tot["pcg_iters"] * (spmv_bytes(N, NB, fp32) + (204 if fp32 else 240) * N) / bw
+    pcg = tot["pcg_iters"] * (spmv_bytes(N, NB, fp32) + (192 if fp32 else 216) * N) / bw
     elem = tot["newton_iters"] * (1592 * T + 261 * N + 148 * E) / bw
     ls = (tot["newton_iters"] + tot["ls_backtracks"] / 4.0) * (112 * T + 84 * N) / bw
     eig = tot["projected"] * 45.6e3 / ((157.3 if fp32 else 78.6) * 1e12)

@@ -50,7 +50,7 @@ struct PcgState {
 template <typename M>
 struct PcgVec {
   const M* vals = nullptr;    // sliced-ELL values
-  const M* pinv = nullptr;    // [9][N] block-Jacobi inverse
+  const M* pinv = nullptr;    // [6][N] block-Jacobi inverse (symmetric, upper triangle)
   double* zd = nullptr;       // [2][N][6] (z, d) records
   double* r = nullptr;        // [N][3] residual
   double* q = nullptr;        // [N][3] H d
@@ -96,7 +96,7 @@ struct Dev {
   double* vslots = nullptr;  // [4T][9]
   double* eslots = nullptr;  // [6T][9]
   double* vals = nullptr;    // [n_slots * 9 * 64], entry c of a block at base + 64 c
-  double* pinv = nullptr;    // [9][N]
+  double* pinv = nullptr;    // [6][N] upper triangle of the symmetric inverse
   uint8_t* spd_ok = nullptr; // [N]
   // Dirichlet
   int32_t* dir_idx = nullptr;  // [N], -1 if free
@@ -109,7 +109,7 @@ struct Dev {
   // mixed precision (null in FP64 scenes)
   float* vals32 = nullptr;  // [n_slots * 9 * 64]: per slot four [64] float2 entry pairs
                             // (0,1) (2,3) (4,5) (6,7), then entry 8 as [64] float
-  float* pinv32 = nullptr;  // [9][N]
+  float* pinv32 = nullptr;  // [6][N]
   double* e = nullptr;      // [N][3] correction of one refinement round
   double* ri = nullptr;     // [N][3] residual of the inner solve
   double* qi = nullptr;     // [N][3] H d of the inner solve

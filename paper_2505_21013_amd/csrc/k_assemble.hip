@@ -48,12 +48,9 @@ __device__ inline void store_diag(const Dev& D, int i, const double hd[6]) {
   D.pinv[0 * N + i] = c00 * id;
   D.pinv[1 * N + i] = c01 * id;
   D.pinv[2 * N + i] = c02 * id;
-  D.pinv[3 * N + i] = c01 * id;
-  D.pinv[4 * N + i] = c11 * id;
-  D.pinv[5 * N + i] = c12 * id;
-  D.pinv[6 * N + i] = c02 * id;
-  D.pinv[7 * N + i] = c12 * id;
-  D.pinv[8 * N + i] = c22 * id;
+  D.pinv[3 * N + i] = c11 * id;
+  D.pinv[4 * N + i] = c12 * id;
+  D.pinv[5 * N + i] = c22 * id;
   D.spd_ok[i] = ok ? 1 : 0;
 }
 
@@ -337,8 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_safety_dir(Dev D) {
   const double g0 = D.g[3 * i], g1 = D.g[3 * i + 1], g2 = D.g[3 * i + 2];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
-    D.dx[3 * i + r] = -(D.pinv[(3 * r) * N + i] * g0 + D.pinv[(3 * r + 1) * N + i] * g1 +
-                        D.pinv[(3 * r + 2) * N + i] * g2);
+    D.dx[3 * i + r] = -(D.pinv[kSym3[r][0] * N + i] * g0 + D.pinv[kSym3[r][1] * N + i] * g1 +
+                        D.pinv[kSym3[r][2] * N + i] * g2);
 }
 
 void launch_safety_dir(const Dev& D, hipStream_t st) {

@@ -54,6 +54,11 @@ __device__ inline double reduce_partials(const double* p, int G, double* lds) {
   return block_sum(s, lds);
 }
 
+// The block-Jacobi inverse of a symmetric 3x3 block is symmetric and stored as
+// its upper triangle, entries (00, 01, 02, 11, 12, 22) in planes [6][N];
+// kSym3[r][c] is the plane of entry (r, c).
+constexpr int kSym3[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+
 // Workgroups are dispatched round-robin over the 8 XCDs.  Map the hardware
 // index so that XCD x owns the contiguous logical chunks [x*G/8, (x+1)*G/8):
 // neighbouring rows then share an L2.  Requires G % 8 == 0.

@@ -141,7 +141,7 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
   D.vslots = alloc.template get<double>(4 * m * 9);
   D.eslots = alloc.template get<double>(6 * m * 9);
   D.vals = alloc.template get<double>(size_t(D.n_slots) * 9 * kSell);
-  D.pinv = alloc.template get<double>(9 * n);
+  D.pinv = alloc.template get<double>(6 * n);
   D.spd_ok = alloc.template get<uint8_t>(n);
   D.dir_idx = alloc.template get<int32_t>(n);
   D.xbar = alloc.template get<double>(3 * n);
@@ -151,7 +151,7 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
   D.rinf = alloc.template get<double>(n);
   if (precision == PPN_MIXED) {
     D.vals32 = alloc.template get<float>(size_t(D.n_slots) * 9 * kSell);
-    D.pinv32 = alloc.template get<float>(9 * n);
+    D.pinv32 = alloc.template get<float>(6 * n);
     D.e = alloc.template get<double>(3 * n);
     D.ri = alloc.template get<double>(3 * n);
     D.qi = alloc.template get<double>(3 * n);
@@ -525,7 +525,7 @@ void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
   constexpr int kMaxRounds = 8;
   constexpr double kMinInner = 1e-6;
   launch_sell_to_f32(D_.vals, D_.vals32, int64_t(D_.n_slots), st_);
-  launch_to_f32(D_.pinv, D_.pinv32, int64_t(9) * D_.N, st_);
+  launch_to_f32(D_.pinv, D_.pinv32, int64_t(6) * D_.N, st_);
   launch_refine_init(D_, st_);
   launch_reduce_pcg(D_, kPartA, 1, st_);
   LAUNCHCHK();
