@@ -126,6 +126,17 @@ struct Dev {
   int32_t* flag = nullptr;  // [4] misc device flags (bad element count, ...)
 };
 
+// Bytes of the FP64 sliced-ELL values (9 entries of 64 rows per slot).
+inline int64_t matrix_bytes(const Dev& D) { return D.n_slots * 9 * 64 * int64_t(sizeof(double)); }
+
+// The PCG product streams an FP64 matrix larger than this with non-temporal
+// loads; a smaller one is read with ordinary loads and stays resident in the
+// 256 MB last-level cache between iterations (measured per PCG iteration,
+// cached against streamed: 23 / 26 us at 32^3 cells, 37 / 41 us at 48^3,
+// 52 / 59 us at 56^3 with its 200 MB matrix; 101 / 91 us at 64^3, 297 MB).
+constexpr int64_t kCacheResidentMatrixBytes = int64_t(224) << 20;
+inline bool stream_matrix(int64_t bytes) { return bytes > kCacheResidentMatrixBytes; }
+
 // ---- launchers (all asynchronous on `st`) --------------------------------
 void launch_precompute(const Dev& D, double rho, hipStream_t st);
 void launch_predict(const Dev& D, hipStream_t st);
@@ -175,11 +186,12 @@ struct PcgJob {
 void launch_pcg_batch_init(const PcgJob<double>* jobs, int n, int total_wg, hipStream_t st);
 void launch_pcg_batch_init(const PcgJob<float>* jobs, int n, int total_wg, hipStream_t st);
 // any_first: some job starts at this iteration (its first product is a
-// separate instance, launched only then).
+// separate instance, launched only then).  matrix_bytes: the jobs' summed
+// FP64 matrix size (selects streaming or cache-resident loads).
 void launch_pcg_batch_iter(const PcgJob<double>* jobs, int n, int total_wg, int j, bool any_first,
-                           hipStream_t st);
+                           int64_t matrix_bytes, hipStream_t st);
 void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j, bool any_first,
-                           hipStream_t st);
+                           int64_t matrix_bytes, hipStream_t st);
 void launch_pcg_batch_gather(const PcgJob<double>* jobs, int n, PcgState* out, hipStream_t st);
 void launch_pcg_batch_gather(const PcgJob<float>* jobs, int n, PcgState* out, hipStream_t st);
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);

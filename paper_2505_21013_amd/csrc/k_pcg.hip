@@ -127,14 +127,18 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
 
 // The 9 entries of the block of (slot, lane).
 // FP64: entry-major, entry e at (slot*9 + e)*64 + lane (nine 512-byte runs).
-// The FP64 matrix (~300 MB at 1.57M tets) is larger than every cache level, so
-// it is streamed with non-temporal loads that keep it from evicting the
-// gathered (z, d) records.
+// kStream: the matrix is larger than the last-level cache (~300 MB at 1.57M
+// tets) and is streamed with non-temporal loads that keep it from evicting the
+// gathered (z, d) records.  Smaller matrices are read with ordinary loads and
+// stay cache-resident from one iteration to the next (measured: 21 against
+// 25 us per PCG iteration on the 122,880-tet beam; 101 against 91 us on the
+// 1.57M-tet cube the other way round).  The choice changes no arithmetic.
+template <bool kStream>
 __device__ __forceinline__ void load_block(const double* __restrict__ vals, int slot, int l,
                                            double w[9]) {
   const double* v = vals + size_t(slot) * (9 * kSell) + l;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) w[e] = __builtin_nontemporal_load(v + e * kSell);
+  for (int e = 0; e < 9; ++e) w[e] = kStream ? __builtin_nontemporal_load(v + e * kSell) : v[e * kSell];
 }
 // FP32: entries paired, pair k = (2k, 2k+1) as a float2 at slot*576 + 2*(64k + lane)
 // for k < 4, entry 8 at slot*576 + 512 + lane: five loads of 512 / 256 bytes.
@@ -143,6 +147,7 @@ __device__ __forceinline__ void load_block(const double* __restrict__ vals, int 
 // iteration to the next (measured: 62 against 74 us per PCG iteration with
 // non-temporal loads on the 1.57M-tet cube).
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <bool kStream>
 __device__ __forceinline__ void load_block(const float* __restrict__ vals, int slot, int l,
                                            float w[9]) {
   const float* base = vals + size_t(slot) * (9 * kSell);
@@ -160,7 +165,7 @@ __device__ __forceinline__ void load_block(const float* __restrict__ vals, int s
 // so that q = H (z + beta d_old) = qz + beta qd needs beta only at the end.
 // The arithmetic and the accumulation are in the matrix type M (FP32 for the
 // FP32 matrix: the gathered FP64 vectors are rounded on load).
-template <typename M>
+template <typename M, bool kStream>
 __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __restrict__ vals,
                                                        const double* __restrict__ zd, bool with_d,
                                                        int g, int l, M qz[3], M qd[3]) {
@@ -177,7 +182,7 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
     const double2 a = p[0], b = p[1];
     const M z0 = M(a.x), z1 = M(a.y), z2 = M(b.x);
     M w[9];
-    load_block(vals, slot, l, w);
+    load_block<kStream>(vals, slot, l, w);
     qz[0] += w[0] * z0 + w[1] * z1 + w[2] * z2;
     qz[1] += w[3] * z0 + w[4] * z1 + w[5] * z2;
     qz[2] += w[6] * z0 + w[7] * z1 + w[8] * z2;
@@ -198,7 +203,7 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
 // the batched kernels too, so that they compile to the same arithmetic as the
 // single-scene kernels (a runtime flag changes which products the compiler
 // fuses into FMAs, and with it the last bits).
-template <typename M, bool kFirst>
+template <typename M, bool kFirst, bool kStream>
 __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, int j, double tol2,
                                               int maxit, int w) {
   __shared__ double lds[16];
@@ -217,7 +222,7 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   const int i = w * kPcgBlock + threadIdx.x;
   const int g = i / kSell, l = i % kSell;
   M qz[3] = {0, 0, 0}, qd[3] = {0, 0, 0};
-  if (g < D.n_groups) sell_row_product_split<M>(D, V.vals, zcur, !kFirst, g, l, qz, qd);
+  if (g < D.n_groups) sell_row_product_split<M, kStream>(D, V.vals, zcur, !kFirst, g, l, qz, qd);
 
   sa = wave_sum(sa);
   sb = wave_sum(sb);
@@ -275,10 +280,10 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   if (threadIdx.x == 0) D.part[kPartKappa * Gp + w] = kap;
 }
 
-template <typename M, bool kFirst>
+template <typename M, bool kFirst, bool kStream>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int j, double tol2,
                                                         int maxit) {
-  pcg_spmv_body<M, kFirst>(D, V, j, tol2, maxit, logical_wg(D.Gp));
+  pcg_spmv_body<M, kFirst, kStream>(D, V, j, tol2, maxit, logical_wg(D.Gp));
 }
 
 // The row's inputs are loaded before the d^T q partials are combined, so both
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int 
 // 768 values of each [N][3] vector: q, r and x are moved between HBM and LDS
 // with unit-stride loads and stores and read per vertex from LDS, instead of
 // three 24-byte-strided accesses per vector and lane.
-template <typename M>
+template <typename M, bool kStream>
 __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V, int j, int w) {
   __shared__ double lds[16];
   __shared__ double sq[3 * kPcgBlock], sr[3 * kPcgBlock], sx[3 * kPcgBlock];
@@ -314,7 +319,8 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
 #pragma unroll
     for (int c = 0; c < 3; ++c) d[c] = znext[6 * size_t(i) + 3 + c];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) P[k] = double(__builtin_nontemporal_load(V.pinv + k * N + i));
+    for (int k = 0; k < 6; ++k)
+      P[k] = double(kStream ? __builtin_nontemporal_load(V.pinv + k * N + i) : V.pinv[k * N + i]);
   }
   const double kap = reduce_partials(D.part + kPartKappa * Gp, Gp, lds);  // synchronises
   if (kap <= 0.0) { pcg_finish(D, w, 1, j + 1); return; }
@@ -352,9 +358,9 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
   }
 }
 
-template <typename M>
+template <typename M, bool kStream>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update(Dev D, PcgVec<M> V, int j) {
-  pcg_update_body<M>(D, V, j, logical_wg(D.Gp));
+  pcg_update_body<M, kStream>(D, V, j, logical_wg(D.Gp));
 }
 
 template <typename T>
@@ -363,16 +369,31 @@ static void pcg_init(const Dev& D, const PcgVec<T>& V, const double* src, double
   k_pcg_init<T><<<D.Gp, kPcgBlock, 0, st>>>(D, V, src, sign);
 }
 
+template <typename T, bool kStream>
+static void pcg_iter_k(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
+                       hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
+  if (ev_spmv_start) (void)hipEventRecord(ev_spmv_start, st);
+  if (j == 0)
+    k_pcg_spmv<T, true, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
+  else
+    k_pcg_spmv<T, false, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
+  if (ev_spmv_stop) (void)hipEventRecord(ev_spmv_stop, st);
+  k_pcg_update<T, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
+}
+
+// The FP32 matrix of the mixed form always fits in the last-level cache.
+template <typename T>
+static bool streamed(int64_t matrix_bytes) {
+  return sizeof(T) == 8 && stream_matrix(matrix_bytes);
+}
+
 template <typename T>
 static void pcg_iter(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                      hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
-  if (ev_spmv_start) (void)hipEventRecord(ev_spmv_start, st);
-  if (j == 0)
-    k_pcg_spmv<T, true><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
+  if (streamed<T>(matrix_bytes(D)))
+    pcg_iter_k<T, true>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
   else
-    k_pcg_spmv<T, false><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
-  if (ev_spmv_stop) (void)hipEventRecord(ev_spmv_stop, st);
-  k_pcg_update<T><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
+    pcg_iter_k<T, false>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
 }
 
 void launch_pcg_init(const Dev& D, const PcgVec<double>& V, const double* src, double sign,
@@ -535,22 +556,22 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init_batch(const PcgJob<M>* _
 
 // Iteration jg of the batch is iteration jg - j0 of each job's own solve.  The
 // kFirst instance serves the jobs at their first iteration, the other the rest.
-template <typename M, bool kFirst>
+template <typename M, bool kFirst, bool kStream>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv_batch(const PcgJob<M>* __restrict__ jobs, int n,
                                                               int jg) {
   int w;
   const PcgJob<M>& J = find_job(jobs, n, w);
   const int j = jg - J.j0;
   if ((j == 0) != kFirst) return;
-  pcg_spmv_body<M, kFirst>(J.D, J.V, j, J.tol2, J.maxit, w);
+  pcg_spmv_body<M, kFirst, kStream>(J.D, J.V, j, J.tol2, J.maxit, w);
 }
 
-template <typename M>
+template <typename M, bool kStream>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_update_batch(const PcgJob<M>* __restrict__ jobs, int n,
                                                                 int jg) {
   int w;
   const PcgJob<M>& J = find_job(jobs, n, w);
-  pcg_update_body<M>(J.D, J.V, jg - J.j0, w);
+  pcg_update_body<M, kStream>(J.D, J.V, jg - J.j0, w);
 }
 
 // out[k] = job k's PcgState (one read-back for the whole batch).
@@ -564,12 +585,21 @@ template <typename M>
 static void batch_init(const PcgJob<M>* jobs, int n, int total_wg, hipStream_t st) {
   k_pcg_init_batch<M><<<total_wg, kPcgBlock, 0, st>>>(jobs, n);
 }
+template <typename M, bool kStream>
+static void batch_iter_k(const PcgJob<M>* jobs, int n, int total_wg, int j, bool any_first,
+                         hipStream_t st) {
+  if (any_first) k_pcg_spmv_batch<M, true, kStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+  k_pcg_spmv_batch<M, false, kStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+  k_pcg_update_batch<M, kStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+}
+// matrix_bytes: the summed matrix size of the jobs (they share the cache).
 template <typename M>
 static void batch_iter(const PcgJob<M>* jobs, int n, int total_wg, int j, bool any_first,
-                       hipStream_t st) {
-  if (any_first) k_pcg_spmv_batch<M, true><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
-  k_pcg_spmv_batch<M, false><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
-  k_pcg_update_batch<M><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+                       int64_t matrix_bytes, hipStream_t st) {
+  if (streamed<M>(matrix_bytes))
+    batch_iter_k<M, true>(jobs, n, total_wg, j, any_first, st);
+  else
+    batch_iter_k<M, false>(jobs, n, total_wg, j, any_first, st);
 }
 template <typename M>
 static void batch_gather(const PcgJob<M>* jobs, int n, PcgState* out, hipStream_t st) {
@@ -583,12 +613,12 @@ void launch_pcg_batch_init(const PcgJob<float>* jobs, int n, int total_wg, hipSt
   batch_init(jobs, n, total_wg, st);
 }
 void launch_pcg_batch_iter(const PcgJob<double>* jobs, int n, int total_wg, int j, bool any_first,
-                           hipStream_t st) {
-  batch_iter(jobs, n, total_wg, j, any_first, st);
+                           int64_t matrix_bytes, hipStream_t st) {
+  batch_iter(jobs, n, total_wg, j, any_first, matrix_bytes, st);
 }
 void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j, bool any_first,
-                           hipStream_t st) {
-  batch_iter(jobs, n, total_wg, j, any_first, st);
+                           int64_t matrix_bytes, hipStream_t st) {
+  batch_iter(jobs, n, total_wg, j, any_first, matrix_bytes, st);
 }
 void launch_pcg_batch_gather(const PcgJob<double>* jobs, int n, PcgState* out, hipStream_t st) {
   batch_gather(jobs, n, out, st);

@@ -225,11 +225,13 @@ bool PcgBatcher::step(Lane& L, std::vector<Job*>& joining, std::vector<Job*>& fi
   const int n = int(L.members.size());
   auto* tab = static_cast<PcgJob<M>*>(L.h_tab[p]);
   int total = 0;
+  int64_t mbytes = 0;
   L.polled[p].clear();
   for (int k = 0; k < n; ++k) {
     const Job& j = *L.members[size_t(k)];
     tab[k] = entry<M>(j.D, vec_of<M>(j.V64, j.V32), j.src, j.sign, j.tol2, j.maxit, total, j.j0);
     total += j.D.Gp;
+    mbytes += matrix_bytes(j.D);
     L.polled[p].push_back(j.id);
   }
   const auto* dtab = static_cast<const PcgJob<M>*>(L.d_tab[p]);
@@ -246,7 +248,7 @@ bool PcgBatcher::step(Lane& L, std::vector<Job*>& joining, std::vector<Job*>& fi
     launch_pcg_batch_init(static_cast<const PcgJob<M>*>(L.d_new), int(joining.size()), tn, st_);
   }
   for (int k = 0; k < kChunk; ++k)
-    launch_pcg_batch_iter(dtab, n, total, L.jg + k, k == 0 && !joining.empty(), st_);
+    launch_pcg_batch_iter(dtab, n, total, L.jg + k, k == 0 && !joining.empty(), mbytes, st_);
   L.jg += kChunk;
   launch_pcg_batch_gather(dtab, n, L.d_state[p], st_);
   BCHK(hipGetLastError());
