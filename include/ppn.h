@@ -61,7 +61,7 @@ typedef enum { PPN_STOP_VEL = 0, PPN_STOP_GRAD_REL = 1 } ppn_stop_mode;
 typedef enum {
   PPN_OK = 0,
   PPN_ERR_ARG = -1,    /* invalid argument or call order */
-  PPN_ERR_MESH = -2,   /* index out of range, or a rest tet with det(Dm) <= 0 */
+  PPN_ERR_MESH = -2,   /* invalid mesh (see ppn_load_mesh), or a rest tet with det(Dm) <= 0 */
   PPN_ERR_OOM = -3,    /* device allocation failed */
   PPN_ERR_DEVICE = -4, /* a HIP call failed (message in ppn_last_error) */
   PPN_ERR_STATE = -5,  /* non-finite positions or velocities */
@@ -150,7 +150,12 @@ ppn_status ppn_scene_destroy(ppn_scene* s);
  * element->slot maps, allocates device memory, computes Dm^-1, V_e and the
  * lumped masses (needs the material; default rho 1000, E 1e5, nu 0.45 until
  * ppn_set_material is called).  Velocities start at zero.  Errors:
- * PPN_ERR_MESH for an index out of range or det(Dm) <= 0. */
+ * PPN_ERR_MESH for an index out of range, a tet that repeats a vertex, a
+ * vertex that belongs to no tet, det(Dm) <= 0, or a mesh beyond the 32-bit
+ * index limits (at most 238,609,294 tets; at most 2^31 sliced-ELL block
+ * positions, about 140M vertices of a regular tet grid); PPN_ERR_OOM when the
+ * device memory does not hold it (about 1.2 KB per tet in PPN_FP64, so one
+ * 288 GB GPU holds about 230M tets). */
 ppn_status ppn_load_mesh(ppn_scene* s, int32_t n_verts, const double* rest_xyz,
                          int32_t n_tets, const int32_t* tets, const double* init_xyz);
 

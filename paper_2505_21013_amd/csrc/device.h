@@ -89,9 +89,9 @@ struct Dev {
   int32_t* eptr = nullptr;       // [E+1]
   int32_t* gslots = nullptr;     // [n_groups] slots of each 64-row group
   int32_t* col = nullptr;        // [n_slots * 64] column of each (slot, lane)
-  int32_t* diag_blk = nullptr;   // [N] value base index of the diagonal block
-  int32_t* eblk_up = nullptr;    // [E] value base index of block (lo, hi)
-  int32_t* eblk_lo = nullptr;    // [E] value base index of block (hi, lo)
+  int32_t* diag_blk = nullptr;   // [N] position (slot * 64 + lane) of the diagonal block
+  int32_t* eblk_up = nullptr;    // [E] position of block (lo, hi)
+  int32_t* eblk_lo = nullptr;    // [E] position of block (hi, lo)
   // slots and matrix
   double* vslots = nullptr;  // [4T][9]
   double* eslots = nullptr;  // [6T][9]
@@ -125,6 +125,12 @@ struct Dev {
   PcgState* pcg = nullptr;
   int32_t* flag = nullptr;  // [4] misc device flags (bad element count, ...)
 };
+
+// Offset of the first value of the sliced-ELL block at position
+// pos = slot * 64 + lane (entry c follows at + 64 c), in 64-bit arithmetic.
+__host__ __device__ inline size_t block_values(int32_t pos) {
+  return size_t(pos >> 6) * (9 * 64) + size_t(pos & 63);
+}
 
 // Bytes of the FP64 sliced-ELL values (9 entries of 64 rows per slot).
 inline int64_t matrix_bytes(const Dev& D) { return D.n_slots * 9 * 64 * int64_t(sizeof(double)); }

@@ -25,7 +25,7 @@ __device__ inline void store_diag(const Dev& D, int i, const double hd[6]) {
   const double di = D.mass[i] / (D.h * D.h) + (D.dir_idx[i] >= 0 ? D.k_dir : 0.0);
   const double a00 = hd[0] + di, a01 = hd[1], a02 = hd[2];
   const double a11 = hd[3] + di, a12 = hd[4], a22 = hd[5] + di;
-  double* vb = D.vals + D.diag_blk[i];
+  double* vb = D.vals + block_values(D.diag_blk[i]);
   vb[0 * kSell] = a00;
   vb[1 * kSell] = a01;
   vb[2 * kSell] = a02;
@@ -62,8 +62,8 @@ __device__ inline void gather_edge(const Dev& D, int k) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) s[c] += sl[c];
   }
-  double* vu = D.vals + D.eblk_up[k];
-  double* vl = D.vals + D.eblk_lo[k];
+  double* vu = D.vals + block_values(D.eblk_up[k]);
+  double* vl = D.vals + block_values(D.eblk_lo[k]);
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll

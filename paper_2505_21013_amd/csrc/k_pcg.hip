@@ -35,6 +35,7 @@
 // 256 / 512-byte run), 4 groups per 256-thread workgroup, workgroups mapped to
 // contiguous row ranges per XCD.  Slot-major storage keeps the wavefronts that
 // walk their groups' slots at the same pace inside a narrow window of memory.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -369,15 +370,24 @@ static void pcg_init(const Dev& D, const PcgVec<T>& V, const double* src, double
   k_pcg_init<T><<<D.Gp, kPcgBlock, 0, st>>>(D, V, src, sign);
 }
 
+// A sampled product (events given) is launched with the events attached to the
+// launch itself, so that their interval is the kernel's execution and not the
+// dispatch gap after the preceding kernel.
 template <typename T, bool kStream>
 static void pcg_iter_k(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                        hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
-  if (ev_spmv_start) (void)hipEventRecord(ev_spmv_start, st);
-  if (j == 0)
+  if (ev_spmv_start && ev_spmv_stop) {
+    if (j == 0)
+      hipExtLaunchKernelGGL(k_pcg_spmv<T, true, kStream>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
+                            ev_spmv_start, ev_spmv_stop, 0, D, V, j, tol2, maxit);
+    else
+      hipExtLaunchKernelGGL(k_pcg_spmv<T, false, kStream>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
+                            ev_spmv_start, ev_spmv_stop, 0, D, V, j, tol2, maxit);
+  } else if (j == 0) {
     k_pcg_spmv<T, true, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
-  else
+  } else {
     k_pcg_spmv<T, false, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
-  if (ev_spmv_stop) (void)hipEventRecord(ev_spmv_stop, st);
+  }
   k_pcg_update<T, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
 }
 

@@ -26,8 +26,9 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
         }
     }
   }
-  if (int64_t(T) * 6 >= (int64_t(1) << 31)) {
-    err = "too many elements for 32-bit slot indices";
+  // Per-element arrays are indexed [k][T] with k < 9 in 32-bit arithmetic.
+  if (int64_t(T) * 9 >= (int64_t(1) << 31)) {
+    err = "too many elements for 32-bit element indices (at most 238,609,294)";
     return false;
   }
   t.n_verts = N;
@@ -37,6 +38,13 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
   t.vptr.assign(N + 1, 0);
   for (int64_t e = 0; e < T; ++e)
     for (int a = 0; a < 4; ++a) t.vptr[tets[4 * e + a] + 1]++;
+  // A vertex outside every element has no mass and no stiffness: its diagonal
+  // block is singular and would leave every Newton system indefinite.
+  for (int32_t i = 0; i < N; ++i)
+    if (t.vptr[i + 1] == 0) {
+      err = "vertex " + std::to_string(i) + " belongs to no tetrahedron";
+      return false;
+    }
   for (int32_t i = 0; i < N; ++i) t.vptr[i + 1] += t.vptr[i];
   std::vector<int32_t> fill(t.vptr.begin(), t.vptr.end() - 1);
   t.vslot.resize(4 * size_t(T));
@@ -132,8 +140,8 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
     t.gslots[i / kSell] = std::max(t.gslots[i / kSell], t.row_ptr[i + 1] - t.row_ptr[i]);
   t.smax = *std::max_element(t.gslots.begin(), t.gslots.end());
   t.n_slots = int64_t(t.smax) * t.n_groups;
-  if (t.n_slots * 9 * kSell >= (int64_t(1) << 31)) {
-    err = "matrix too large for 32-bit sliced-ELL indices";
+  if (t.n_slots * kSell >= (int64_t(1) << 31)) {
+    err = "matrix too large for 32-bit sliced-ELL block positions";
     return false;
   }
   t.sell_col.assign(size_t(t.n_slots) * kSell, 0);
@@ -147,7 +155,7 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
         if (i < N && s < t.row_ptr[i + 1] - t.row_ptr[i]) {
           const int32_t k = t.row_ptr[i] + s;
           c = t.col[k];
-          t.csr_base[k] = int32_t(slot * 9 * kSell + l);
+          t.csr_base[k] = int32_t(slot * kSell + l);
         }
         t.sell_col[size_t(slot) * kSell + l] = c;
       }

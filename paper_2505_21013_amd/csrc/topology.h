@@ -58,7 +58,9 @@ struct Topology {
   int64_t n_slots = 0;              // smax * n_groups block rows of 64
   std::vector<int32_t> gslots;      // [n_groups]
   std::vector<int32_t> sell_col;    // [n_slots * 64]
-  std::vector<int32_t> csr_base;    // [NB] value base index of each CSR block
+  // Block positions slot * 64 + lane (the values of the block start at
+  // slot * 9 * 64 + lane, a 64-bit offset: see block_values()).
+  std::vector<int32_t> csr_base;    // [NB] position of each CSR block
   std::vector<int32_t> diag_base;   // [N]
   std::vector<int32_t> eup_base;    // [E]
   std::vector<int32_t> elo_base;    // [E]
@@ -67,7 +69,8 @@ struct Topology {
 constexpr int kSell = 64;  // rows per sliced-ELL group (one wavefront)
 
 // Builds the topology from tets [T][4] (AoS, 0-based).  Returns false and sets
-// err when an index is out of range or an element repeats a vertex.
+// err when an index is out of range, an element repeats a vertex, a vertex
+// belongs to no element, or the mesh exceeds the 32-bit index limits.
 bool build_topology(int32_t n_verts, int32_t n_tets, const int32_t* tets, Topology& out,
                     std::string& err);
 

@@ -3,7 +3,8 @@
 * Two fresh scenes stepping the same schedule produce identical bits.
 * A run restored from a checkpoint (positions and velocities after step 3)
   continues with the same bits as the uninterrupted run.
-* Non-finite states and targets, inverted rest tetrahedra and out-of-range
+* Non-finite states and targets, inverted rest tetrahedra, vertices outside
+  every tetrahedron, repeated or out-of-range vertex indices and out-of-range
   parameters are rejected with the documented status before anything runs.
 * Forced fallback to PN (alpha so small that delta drops below eps_delta within
   the first inner rounds) and forced line-search failure (Armijo constant
@@ -88,6 +89,22 @@ def test_bad_inputs_are_rejected():
     tets[5, [1, 2]] = tets[5, [2, 1]]
     s = Scene()
     assert _code(lambda: (s.ppn_load_mesh(X, tets), s.ppn_set_material(1000.0, 1e5, 0.45))) == -2
+    s.close()
+    # a vertex that belongs to no tetrahedron (singular diagonal block)
+    X2 = np.vstack([X, X[-1:] + 1.0])
+    s = Scene()
+    with pytest.raises(PPNError, match="belongs to no tetrahedron") as e:
+        s.ppn_load_mesh(X2, kuhn_grid(2, 2, 2)[1])
+    assert e.value.code == -2
+    s.close()
+    # a tet that repeats a vertex; an index out of range
+    bad = kuhn_grid(2, 2, 2)[1].copy()
+    bad[0, 1] = bad[0, 0]
+    s = Scene()
+    assert _code(lambda: s.ppn_load_mesh(X, bad)) == -2
+    bad = kuhn_grid(2, 2, 2)[1].copy()
+    bad[3, 2] = len(X)
+    assert _code(lambda: s.ppn_load_mesh(X, bad)) == -2
     s.close()
 
 
