@@ -10,7 +10,7 @@
 //                  the 9 entries of the 64 rows' blocks are entry-major (value
 //                  (slot*9 + c)*64 + lane), so every load of the matrix product is
 //                  one contiguous 512-byte run
-//   block-Jacobi   SoA [9][N]: inverse of each diagonal block
+//   block-Jacobi   SoA [6][N]: inverse of each diagonal block (symmetric: upper triangle)
 //   mixed precision (only when requested): FP32 copies of the sliced-ELL
 //                  values and of the block-Jacobi inverse, three more [N][3]
 //                  vectors for the inner solve (correction, residual, H d)
