@@ -40,9 +40,10 @@ struct PcgState {
   int32_t done;
   int32_t ind;
   int32_t iters;
-  int32_t pad;
+  int32_t j_rr;    // iteration of the last product that went on (-1 before the first)
   double rr0;      // r0^T r0
   double rz[2];    // r_j^T z_j by iteration parity (beta of the next direction, alpha)
+  double rr;       // r^T r at iteration j_rr (the host sizes its launch chunks from it)
 };
 
 // Matrix (type M: FP64, or FP32 in the mixed-precision path) and FP64

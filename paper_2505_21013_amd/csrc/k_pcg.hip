@@ -99,6 +99,7 @@ __device__ __forceinline__ void pcg_init_body(const Dev& D, const PcgVec<M>& V, 
     D.pcg->done = 0;
     D.pcg->ind = 0;
     D.pcg->iters = 0;
+    D.pcg->j_rr = -1;
   }
 }
 
@@ -246,13 +247,19 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
     if (w == 0 && threadIdx.x == 0) {
       D.pcg->rr0 = rr;
       D.pcg->rz[0] = rz;
+      D.pcg->rr = rr;
+      D.pcg->j_rr = 0;
     }
   } else {
     if (rr <= tol2 * D.pcg->rr0) { pcg_finish(D, w, 0, j); return; }
     if (rz <= 0.0) { pcg_finish(D, w, 1, j); return; }
     if (j >= maxit) { pcg_finish(D, w, 0, j); return; }
     beta = rz / D.pcg->rz[(j - 1) & 1];
-    if (w == 0 && threadIdx.x == 0) D.pcg->rz[j & 1] = rz;
+    if (w == 0 && threadIdx.x == 0) {
+      D.pcg->rz[j & 1] = rz;
+      D.pcg->rr = rr;
+      D.pcg->j_rr = j;
+    }
   }
   double kap = 0.0;
   if (i < D.N) {

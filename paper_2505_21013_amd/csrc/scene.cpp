@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <limits>
 
@@ -26,6 +27,38 @@ static void fail(const std::string& m, ppn_status c = PPN_ERR_ARG) { throw HipEr
 // Every kProfileEvery-th PCG matrix product is bracketed by timing events when
 // profiling is on (sampling keeps the events from perturbing the launch stream).
 constexpr int kProfileEvery = 16;
+
+// Size of the next chunk of PCG iterations to enqueue (from iteration jend on)
+// after reading the state of the chunk before the one in flight.  The device
+// takes every stop decision; launches past it return at once, so the chunk
+// size only trades such empty launches against host round trips.  Once two
+// residuals are known (r0 and the last one read), the decay per iteration
+// between them predicts where |r| meets the tolerance; the chunk ends there
+// plus kChunkMargin iterations (at least kChunkMin, at most kChunkMax).
+// Without a prediction (the residual grew, or none yet) chunks double.
+constexpr int kChunkMin = 4, kChunkMax = 32, kChunkMargin = 2;
+static int next_chunk(const PcgState& S, double tol2, int jend, int chunk, int& j_prev,
+                      double& rr_prev) {
+  int next = std::min(2 * chunk, kChunkMax);
+  if (S.j_rr < 0 || !(S.rr > 0.0) || !(S.rr0 > 0.0)) return next;
+  if (j_prev < 0) {
+    j_prev = 0;
+    rr_prev = S.rr0;
+  }
+  if (S.j_rr > j_prev && S.rr < rr_prev) {
+    const double lr = std::log(S.rr / rr_prev) / double(S.j_rr - j_prev);
+    const double rem = std::log(tol2 * S.rr0 / S.rr) / lr;  // iterations after j_rr
+    if (std::isfinite(rem)) {
+      const double target = double(S.j_rr) + std::max(rem, 0.0) + kChunkMargin;
+      next = int(std::min<double>(kChunkMax, std::max<double>(kChunkMin, std::ceil(target) - jend)));
+    }
+  }
+  if (S.j_rr > j_prev) {
+    j_prev = S.j_rr;
+    rr_prev = S.rr;
+  }
+  return next;
+}
 
 void params_defaults(ppn_params* p) {
   std::memset(p, 0, sizeof(*p));
@@ -448,8 +481,9 @@ void Scene::run_pcg(const PcgVec<T>& V, const double* src, double sign, double r
   const double tol2 = rtol * rtol;
   // Iterations are enqueued in chunks; the status of chunk c-1 is read while
   // chunk c runs, so launches past convergence (which return at once) are at
-  // most two chunks.
-  int j = 0, chunk = 8, slot = 0;
+  // most two chunks, whose sizes next_chunk() fits to the predicted end.
+  int j = 0, chunk = 8, slot = 0, j_prev = -1;
+  double rr_prev = 0.0;
   bool pending = false;
   while (j <= maxit) {
     const int jend = std::min(j + chunk, maxit + 1);
@@ -472,10 +506,12 @@ void Scene::run_pcg(const PcgVec<T>& V, const double* src, double sign, double r
     if (pending) {
       HIPCHK(hipEventSynchronize(ev_[slot ^ 1]));
       if (hpcg_[slot ^ 1].done) break;
+      chunk = next_chunk(hpcg_[slot ^ 1], tol2, jend, chunk, j_prev, rr_prev);
+    } else {
+      chunk = std::min(chunk * 2, kChunkMax);
     }
     pending = true;
     slot ^= 1;
-    chunk = std::min(chunk * 2, 32);
   }
   HIPCHK(hipMemcpyAsync(&hpcg_[2], D_.pcg, sizeof(PcgState), hipMemcpyDeviceToHost, st_));
   sync();
