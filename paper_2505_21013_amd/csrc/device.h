@@ -7,9 +7,9 @@
 //   edge slots     AoS [6T][9]: off-diagonal block, row-major, global orientation
 //   BCSR values    sliced ELL: rows in groups of 64 (one wavefront), slot-major
 //                  (slot s of group g is block row s*n_groups + g); per block row
-//                  the 9 entries of the 64 rows' blocks are entry-major (value
-//                  (slot*9 + c)*64 + lane), so every load of the matrix product is
-//                  one contiguous 512-byte run
+//                  the 64 rows' blocks as four entry pairs [4][64][2] and entry 8
+//                  [64] (value_index), so every load of the matrix product is one
+//                  contiguous 1024- or 512-byte run
 //   block-Jacobi   SoA [6][N]: inverse of each diagonal block (symmetric: upper triangle)
 //   mixed precision (only when requested): FP32 copies of the sliced-ELL
 //                  values and of the block-Jacobi inverse, three more [N][3]
@@ -127,10 +127,15 @@ struct Dev {
   int32_t* flag = nullptr;  // [4] misc device flags (bad element count, ...)
 };
 
-// Offset of the first value of the sliced-ELL block at position
-// pos = slot * 64 + lane (entry c follows at + 64 c), in 64-bit arithmetic.
-__host__ __device__ inline size_t block_values(int32_t pos) {
-  return size_t(pos >> 6) * (9 * 64) + size_t(pos & 63);
+// Index of entry e (row-major 3x3) of the sliced-ELL block at position
+// pos = slot * 64 + lane, in 64-bit arithmetic.  Per slot the 64 lanes'
+// blocks take 9 * 64 values: entries (0,1) (2,3) (4,5) (6,7) as pairs,
+// [4][64][2], then entry 8 as [64]; a lane reads its block with four 16-byte
+// loads and one 8-byte load, each one contiguous run over the wavefront.
+__host__ __device__ inline size_t value_index(int32_t pos, int e) {
+  const size_t base = size_t(pos >> 6) * (9 * 64);
+  const size_t lane = size_t(pos & 63);
+  return e < 8 ? base + size_t(e >> 1) * 128 + 2 * lane + size_t(e & 1) : base + 512 + lane;
 }
 
 // Bytes of the FP64 sliced-ELL values (9 entries of 64 rows per slot).

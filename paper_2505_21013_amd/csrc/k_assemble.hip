@@ -25,16 +25,10 @@ __device__ inline void store_diag(const Dev& D, int i, const double hd[6]) {
   const double di = D.mass[i] / (D.h * D.h) + (D.dir_idx[i] >= 0 ? D.k_dir : 0.0);
   const double a00 = hd[0] + di, a01 = hd[1], a02 = hd[2];
   const double a11 = hd[3] + di, a12 = hd[4], a22 = hd[5] + di;
-  double* vb = D.vals + block_values(D.diag_blk[i]);
-  vb[0 * kSell] = a00;
-  vb[1 * kSell] = a01;
-  vb[2 * kSell] = a02;
-  vb[3 * kSell] = a01;
-  vb[4 * kSell] = a11;
-  vb[5 * kSell] = a12;
-  vb[6 * kSell] = a02;
-  vb[7 * kSell] = a12;
-  vb[8 * kSell] = a22;
+  const int32_t pb = D.diag_blk[i];
+  const double a[9] = {a00, a01, a02, a01, a11, a12, a02, a12, a22};
+#pragma unroll
+  for (int e = 0; e < 9; ++e) D.vals[value_index(pb, e)] = a[e];
   const double c00 = a11 * a22 - a12 * a12;
   const double c01 = a02 * a12 - a01 * a22;
   const double c02 = a01 * a12 - a02 * a11;
@@ -62,14 +56,13 @@ __device__ inline void gather_edge(const Dev& D, int k) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) s[c] += sl[c];
   }
-  double* vu = D.vals + block_values(D.eblk_up[k]);
-  double* vl = D.vals + block_values(D.eblk_lo[k]);
+  const int32_t pu = D.eblk_up[k], pl = D.eblk_lo[k];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      vu[(3 * r + c) * kSell] = s[3 * r + c];
-      vl[(3 * c + r) * kSell] = s[3 * r + c];
+      D.vals[value_index(pu, 3 * r + c)] = s[3 * r + c];
+      D.vals[value_index(pl, 3 * c + r)] = s[3 * r + c];
     }
 }
 

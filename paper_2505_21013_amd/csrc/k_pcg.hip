@@ -109,38 +109,29 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, cons
   pcg_init_body<M>(D, V, src, sign, logical_wg(D.Gp));
 }
 
-// q_i = sum over the row's slots of B d_col, d read from a plain [N][3] vector (FP64).
-__device__ __forceinline__ void sell_row_product(const Dev& D, const double* __restrict__ src,
-                                                 int g, int l, double& q0, double& q1,
-                                                 double& q2) {
-  const int S = D.gslots[g];
-  q0 = q1 = q2 = 0.0;
-#pragma unroll 4
-  for (int s = 0; s < S; ++s) {
-    const int slot = s * D.n_groups + g;
-    const int c = D.col[slot * kSell + l];
-    const double d0 = src[3 * c], d1 = src[3 * c + 1], d2 = src[3 * c + 2];
-    const double* v = D.vals + size_t(slot) * (9 * kSell) + l;
-    q0 += v[0 * kSell] * d0 + v[1 * kSell] * d1 + v[2 * kSell] * d2;
-    q1 += v[3 * kSell] * d0 + v[4 * kSell] * d1 + v[5 * kSell] * d2;
-    q2 += v[6 * kSell] * d0 + v[7 * kSell] * d1 + v[8 * kSell] * d2;
-  }
-}
-
 // The 9 entries of the block of (slot, lane).
-// FP64: entry-major, entry e at (slot*9 + e)*64 + lane (nine 512-byte runs).
+// FP64: entries paired, pair k = (2k, 2k+1) at slot*576 + 128k + 2*lane, entry 8
+// at slot*576 + 512 + lane: four 16-byte loads (1024-byte runs over the
+// wavefront) and one 8-byte load.
 // kStream: the matrix is larger than the last-level cache (~300 MB at 1.57M
 // tets) and is streamed with non-temporal loads that keep it from evicting the
 // gathered (z, d) records.  Smaller matrices are read with ordinary loads and
 // stay cache-resident from one iteration to the next (measured: 21 against
 // 25 us per PCG iteration on the 122,880-tet beam; 101 against 91 us on the
 // 1.57M-tet cube the other way round).  The choice changes no arithmetic.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <bool kStream>
 __device__ __forceinline__ void load_block(const double* __restrict__ vals, int slot, int l,
                                            double w[9]) {
-  const double* v = vals + size_t(slot) * (9 * kSell) + l;
+  const double* base = vals + size_t(slot) * (9 * kSell);
+  const f64x2* v2 = reinterpret_cast<const f64x2*>(base) + l;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) w[e] = kStream ? __builtin_nontemporal_load(v + e * kSell) : v[e * kSell];
+  for (int k = 0; k < 4; ++k) {
+    const f64x2 p = kStream ? __builtin_nontemporal_load(v2 + k * kSell) : v2[k * kSell];
+    w[2 * k] = p.x;
+    w[2 * k + 1] = p.y;
+  }
+  w[8] = kStream ? __builtin_nontemporal_load(base + 8 * kSell + l) : base[8 * kSell + l];
 }
 // FP32: entries paired, pair k = (2k, 2k+1) as a float2 at slot*576 + 2*(64k + lane)
 // for k < 4, entry 8 at slot*576 + 512 + lane: five loads of 512 / 256 bytes.
@@ -161,6 +152,25 @@ __device__ __forceinline__ void load_block(const float* __restrict__ vals, int s
     w[2 * k + 1] = p.y;
   }
   w[8] = base[8 * kSell + l];
+}
+
+// q_i = sum over the row's slots of B d_col, d read from a plain [N][3] vector (FP64).
+__device__ __forceinline__ void sell_row_product(const Dev& D, const double* __restrict__ src,
+                                                 int g, int l, double& q0, double& q1,
+                                                 double& q2) {
+  const int S = D.gslots[g];
+  q0 = q1 = q2 = 0.0;
+#pragma unroll 4
+  for (int s = 0; s < S; ++s) {
+    const int slot = s * D.n_groups + g;
+    const int c = D.col[slot * kSell + l];
+    const double d0 = src[3 * c], d1 = src[3 * c + 1], d2 = src[3 * c + 2];
+    double v[9];
+    load_block<false>(D.vals, slot, l, v);
+    q0 += v[0] * d0 + v[1] * d1 + v[2] * d2;
+    q1 += v[3] * d0 + v[4] * d1 + v[5] * d2;
+    q2 += v[6] * d0 + v[7] * d1 + v[8] * d2;
+  }
 }
 
 // Split product over the gathered (z, d_old) records: qz = H z and qd = H d_old,
@@ -466,14 +476,16 @@ __global__ __launch_bounds__(kBlock) void k_sell_to_f32(const double* __restrict
   for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n_slots * kSell; k += stride) {
     const int64_t slot = k / kSell;
     const int l = int(k % kSell);
-    const double* v = src + slot * (9 * kSell) + l;
+    const double* v = src + slot * (9 * kSell);
+    const f64x2* v2 = reinterpret_cast<const f64x2*>(v) + l;
     float* o = dst + slot * (9 * kSell);
     float2* o2 = reinterpret_cast<float2*>(o) + l;
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-      o2[p * kSell] = make_float2(float(__builtin_nontemporal_load(v + (2 * p) * kSell)),
-                                  float(__builtin_nontemporal_load(v + (2 * p + 1) * kSell)));
-    o[8 * kSell + l] = float(__builtin_nontemporal_load(v + 8 * kSell));
+    for (int p = 0; p < 4; ++p) {
+      const f64x2 e = __builtin_nontemporal_load(v2 + p * kSell);
+      o2[p * kSell] = make_float2(float(e.x), float(e.y));
+    }
+    o[8 * kSell + l] = float(__builtin_nontemporal_load(v + 8 * kSell + l));
   }
 }
 

@@ -822,7 +822,7 @@ void Scene::eval_hessian(const double* x, const uint8_t* mask, int32_t* row_ptr,
     HIPCHK(hipMemcpyAsync(sell.data(), D_.vals, sell.size() * 8, hipMemcpyDeviceToHost, st_));
     sync();
     for (size_t b = 0; b < NB; ++b)
-      for (int c = 0; c < 9; ++c) vals[9 * b + c] = sell[block_values(topo_.csr_base[b]) + size_t(c) * kSell];
+      for (int c = 0; c < 9; ++c) vals[9 * b + c] = sell[value_index(topo_.csr_base[b], c)];
   }
   if (row_ptr) std::copy(topo_.row_ptr.begin(), topo_.row_ptr.end(), row_ptr);
   if (col) std::copy(topo_.col.begin(), topo_.col.end(), col);

@@ -49,17 +49,17 @@ struct Topology {
   // (kSell), group g using gslots[g] = its longest row.  Storage is slot-major:
   // slot s of group g is block row (s * n_groups + g), s < smax (the longest row
   // of the mesh), so that wavefronts walking their groups' slots in step read
-  // neighbouring memory.  Entry c of the block in (slot s, group g, lane l)
-  // lives at value index ((s * n_groups + g) * 9 + c) * 64 + l; its column at
-  // (s * n_groups + g) * 64 + l.  Slots past a row's end hold column = the row
+  // neighbouring memory.  The block in (slot s, group g, lane l) has position
+  // (s * n_groups + g) * 64 + l: its column is stored there and its values at
+  // value_index(position, entry) (device.h).  Slots past a row's end hold column = the row
   // itself and zero values; slots past a group's end are never read.
   int32_t n_groups = 0;
   int32_t smax = 0;
   int64_t n_slots = 0;              // smax * n_groups block rows of 64
   std::vector<int32_t> gslots;      // [n_groups]
   std::vector<int32_t> sell_col;    // [n_slots * 64]
-  // Block positions slot * 64 + lane (the values of the block start at
-  // slot * 9 * 64 + lane, a 64-bit offset: see block_values()).
+  // Block positions slot * 64 + lane (the block's values are addressed in
+  // 64-bit arithmetic from the position: value_index() in device.h).
   std::vector<int32_t> csr_base;    // [NB] position of each CSR block
   std::vector<int32_t> diag_base;   // [N]
   std::vector<int32_t> eup_base;    // [E]
