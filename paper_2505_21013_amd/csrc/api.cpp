@@ -45,6 +45,13 @@ ppn_status bad_handle() {
   return PPN_ERR_ARG;
 }
 
+// A NULL pointer argument of a call on a valid scene.
+ppn_status null_arg(ppn_scene* s, const char* name) {
+  g_error = std::string(name) + " must not be NULL";
+  if (s && s->impl) s->impl->last_error = g_error;
+  return PPN_ERR_ARG;
+}
+
 }  // namespace
 
 #define IMPL(s)                     \
@@ -54,7 +61,10 @@ ppn_status bad_handle() {
 extern "C" {
 
 ppn_status ppn_params_default(ppn_params* out) {
-  if (!out) return bad_handle();
+  if (!out) {
+    g_error = "out must not be NULL";
+    return PPN_ERR_ARG;
+  }
   ppn::params_defaults(out);
   return PPN_OK;
 }
@@ -133,7 +143,7 @@ ppn_status ppn_set_dirichlet(ppn_scene* s, int32_t n, const int32_t* ids, const 
 
 ppn_status ppn_set_params(ppn_scene* s, const ppn_params* p) {
   IMPL(s);
-  if (!p) return bad_handle();
+  if (!p) return null_arg(s, "p");
   return guarded(s, [&] {
     S.set_params(*p);
     return PPN_OK;
@@ -147,7 +157,7 @@ ppn_status ppn_newton_step(ppn_scene* s, int32_t mode, ppn_step_stats* out) {
 
 ppn_status ppn_get_positions(ppn_scene* s, double* out) {
   IMPL(s);
-  if (!out) return bad_handle();
+  if (!out) return null_arg(s, "out");
   return guarded(s, [&] {
     S.get_positions(out);
     return PPN_OK;
@@ -156,7 +166,7 @@ ppn_status ppn_get_positions(ppn_scene* s, double* out) {
 
 ppn_status ppn_get_positions_dev(ppn_scene* s, void* out_dev, void* hip_stream) {
   IMPL(s);
-  if (!out_dev) return bad_handle();
+  if (!out_dev) return null_arg(s, "out_dev");
   return guarded(s, [&] {
     S.get_positions_dev(out_dev, static_cast<hipStream_t>(hip_stream));
     return PPN_OK;
@@ -181,7 +191,7 @@ ppn_status ppn_set_state(ppn_scene* s, const double* x, const double* v) {
 
 ppn_status ppn_get_last_stats(ppn_scene* s, ppn_step_stats* out) {
   IMPL(s);
-  if (!out) return bad_handle();
+  if (!out) return null_arg(s, "out");
   *out = S.last_stats;
   return PPN_OK;
 }
@@ -217,7 +227,7 @@ ppn_status ppn_set_profiling(ppn_scene* s, int32_t enable) {
 
 ppn_status ppn_trace_count(ppn_scene* s, int32_t* count) {
   IMPL(s);
-  if (!count) return bad_handle();
+  if (!count) return null_arg(s, "count");
   *count = int32_t(S.trace.size());
   return PPN_OK;
 }
@@ -238,7 +248,7 @@ ppn_status ppn_trace_get(ppn_scene* s, int32_t i, ppn_iter_record* rec, int32_t*
 
 ppn_status ppn_eval_gradient(ppn_scene* s, const double* x, double* g_out) {
   IMPL(s);
-  if (!g_out) return bad_handle();
+  if (!g_out) return null_arg(s, "g_out");
   return guarded(s, [&] {
     S.eval_gradient(x, g_out);
     return PPN_OK;
