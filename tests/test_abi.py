@@ -53,4 +53,7 @@ def test_host_side_errors_without_gpu():
     assert lib.ppn_scene_create(ctypes.byref(h), None, 7) == -1  # unknown precision, before touching HIP
     assert b"PPN_MIXED" in lib.ppn_last_error(None)
     assert lib.ppn_newton_step(None, 2, None) == -1
+    assert b"NULL scene handle" in lib.ppn_last_error(None)
+    assert lib.ppn_params_default(None) == -1
+    assert b"out must not be NULL" in lib.ppn_last_error(None)
     assert lib.ppn_project_batch_dev(None, None, 4, 1e-8, None) == -1
