@@ -333,7 +333,7 @@ ppn_status ppn_engine_get_info(ppn_engine* e, ppn_engine_info* out);
  * time run in shared launches (one matrix-product and one update launch per
  * iteration for all of them, each workgroup working for one scene), which
  * removes the per-scene launch latency of small scenes.  Solves join and
- * leave the running batch at chunk boundaries (every 16 iterations).
+ * leave the running batch at chunk boundaries (every 6 iterations).
  * Results are unchanged bit for bit.  Off by default.  PPN_ERR_STATE unless
  * the engine is idle. */
 ppn_status ppn_engine_set_pcg_batching(ppn_engine* e, int32_t enable);
