@@ -3,7 +3,8 @@
 * Each result is bit-identical alone and in the mix: the same requests run one
   scene at a time on one worker, all at once on several workers (their kernels
   overlapping on the device), with their PCG solves batched into shared
-  launches, and through the single-scene API.
+  launches (one precision at a time, and FP64 and mixed-form scenes together),
+  and through the single-scene API.
 * Admission by footprint: with a budget for two scenes, four scenes take turns
   in device memory (evictions keep the state on the host) with unchanged results.
 * Against the FP64 oracle: rotated blocks of the batched workload, stepped in the
@@ -92,6 +93,28 @@ def test_engine_pcg_batching_changes_nothing(precision):
         for n, (a, b) in enumerate(zip(alone[i], mix[i])):
             diff = {k: (a[k], b[k]) for k in KEYS if a[k] != b[k]}
             assert not diff, (scenes[i].name, n + 1, diff)
+        assert np.array_equal(st_alone[i][0], st_mix[i][0]) and np.array_equal(st_alone[i][1], st_mix[i][1])
+
+
+def test_engine_pcg_batching_mixed_precisions_together():
+    """FP64 and mixed-form scenes in one batching engine: the batcher runs its
+    FP64-matrix and FP32-matrix lanes side by side, and every scene keeps the
+    bits of its unbatched run in its own precision."""
+    scenes = _small_scenes(6)
+    precs = [PPN_FP64 if i % 2 == 0 else PPN_MIXED for i in range(len(scenes))]
+    with Engine(n_workers=1) as e1:
+        ids1 = [e1.add_scene(sc, precision=p) for sc, p in zip(scenes, precs)]
+        alone, st_alone = _run(e1, scenes, ids1, 3, interleave=False)
+    with Engine(n_workers=6) as eb:
+        eb.ppn_engine_set_pcg_batching(True)
+        idsb = [eb.add_scene(sc, precision=p) for sc, p in zip(scenes, precs)]
+        mix, st_mix = _run(eb, scenes, idsb, 3, interleave=True)
+        info = eb.ppn_engine_get_info()
+    assert info["pcg_batches"] > 0, info
+    for i in range(len(scenes)):
+        for n, (a, b) in enumerate(zip(alone[i], mix[i])):
+            diff = {k: (a[k], b[k]) for k in KEYS if a[k] != b[k]}
+            assert not diff, (scenes[i].name, precs[i], n + 1, diff)
         assert np.array_equal(st_alone[i][0], st_mix[i][0]) and np.array_equal(st_alone[i][1], st_mix[i][1])
 
 
