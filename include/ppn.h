@@ -160,24 +160,39 @@ ppn_status ppn_load_mesh(ppn_scene* s, int32_t n_verts, const double* rest_xyz,
                          int32_t n_tets, const int32_t* tets, const double* init_xyz);
 
 /* Density [kg/m^3] and Young's modulus / Poisson ratio, either one value each
- * (per_element = 0) or one per tet (per_element = 1, arrays of n_tets).
- * Requires 0 <= nu < 0.5, E >= 0, rho > 0. */
+ * (per_element = 0) or one per tet (per_element = 1, arrays of n_tets), of the
+ * Stable Neo-Hookean material (Sec. 5.1); recomputes the lumped masses.
+ * PPN_ERR_ARG unless 0 <= nu < 0.5, E >= 0, rho > 0 (or per_element without
+ * a loaded mesh); PPN_ERR_MESH if a rest tet has det(Dm) <= 0. */
 ppn_status ppn_set_material(ppn_scene* s, double rho, const double* E, const double* nu,
                             int32_t per_element);
 
-/* Time step h [s] and gravity [3] (m/s^2). */
+/* Time step h [s] of the backward-Euler potential (Sec. 3, Eq. (1)) and
+ * gravity [3] (m/s^2; NULL keeps the current value).  PPN_ERR_ARG unless h is
+ * finite and > 0. */
 ppn_status ppn_set_time_step(ppn_scene* s, double dt, const double* gravity);
 
-/* Dirichlet penalty set: n vertex ids (any order, no duplicates) and their
- * targets [n][3] at the END of the next time step.  Replaces the previous
- * set; call again before each step to move the targets. */
+/* Dirichlet penalty set (Sec. 5.1, penalty potentials with stiffness
+ * k_dirichlet): n vertex ids (any order, no duplicates) and their targets
+ * [n][3] at the END of the next time step.  Replaces the previous set; call
+ * again before each step to move the targets.  PPN_ERR_ARG for an id out of
+ * range or repeated, a non-finite target, or no loaded mesh. */
 ppn_status ppn_set_dirichlet(ppn_scene* s, int32_t n, const int32_t* vert_ids,
                              const double* target_xyz);
 
+/* Parameters of Algorithm 1 and of the solvers (defaults: ppn_params_default).
+ * PPN_ERR_ARG, with nothing changed, unless 0 < alpha < 1, beta >= 1,
+ * eps_clamp > 0, eps_delta >= 0, 0 < pcg_rtol < 1, pcg_maxit >= 1, a known
+ * stop_mode, stop_tol >= 0, newton_maxit >= 1, ls_maxit >= 0, pdn_countdown
+ * >= 0, 0 < armijo_c < 1, k_dirichlet >= 0 and eig_mirror in {0, 1}. */
 ppn_status ppn_set_params(ppn_scene* s, const ppn_params* p);
 
 /* Advance one time step with the given Newton variant (Algorithm 1 for
- * PPN_PPN).  out may be NULL.  Returns PPN_OK, a warning, or an error. */
+ * PPN_PPN; Sec. 2.2 and Sec. 5.1 for PN and PDN).  out may be NULL.  Returns
+ * PPN_OK; PPN_WARN_NOT_CONVERGED after newton_maxit iterations or
+ * PPN_WARN_LS_FAIL when the line search fails (the state advanced up to that
+ * iteration); PPN_ERR_ARG for an unknown mode or no mesh; PPN_ERR_STATE for a
+ * non-finite gradient; PPN_ERR_DEVICE for a HIP failure. */
 ppn_status ppn_newton_step(ppn_scene* s, int32_t mode, ppn_step_stats* out);
 
 /* Current positions: host copy [n_verts][3], or device-to-device copy into a
@@ -185,8 +200,10 @@ ppn_status ppn_newton_step(ppn_scene* s, int32_t mode, ppn_step_stats* out);
 ppn_status ppn_get_positions(ppn_scene* s, double* out_xyz);
 ppn_status ppn_get_positions_dev(ppn_scene* s, void* out_dev, void* hip_stream);
 
-/* Checkpoint / restore of the time-stepping state (positions, velocities).
- * delta and the PDN countdown are per-step and need no saving. */
+/* Checkpoint / restore of the time-stepping state (positions, velocities),
+ * [n_verts][3] each; set_state refuses non-finite values with PPN_ERR_STATE.
+ * delta and the PDN countdown are per-step (Algorithm 1 resets them) and need
+ * no saving. */
 ppn_status ppn_get_state(ppn_scene* s, double* x, double* v);
 ppn_status ppn_set_state(ppn_scene* s, const double* x, const double* v);
 
@@ -233,7 +250,7 @@ ppn_status ppn_eval_element_hessians(ppn_scene* s, const double* x, const uint8_
 ppn_status ppn_eval_hessian(ppn_scene* s, const double* x, const uint8_t* proj_mask,
                             int32_t* row_ptr, int32_t* col, double* vals);
 
-/* Selection of Algorithm 1 on a caller-given assembled gradient g [3 n_verts]:
+/* Selection of Algorithm 1 (Sec. 4) on a caller-given assembled gradient g [3 n_verts]:
  * mask_out[e] = 1 iff proj_in[e] == 0 and (|S^e g|_inf > delta or
  * delta <= eps_delta).  count_out receives the number of ones. */
 ppn_status ppn_select(ppn_scene* s, const double* g, double delta, const uint8_t* proj_in,
@@ -245,11 +262,13 @@ ppn_status ppn_select(ppn_scene* s, const double* g, double delta, const uint8_t
 ppn_status ppn_solve(ppn_scene* s, const double* x, const uint8_t* proj_mask, double* dx_out,
                      int32_t* ind_out, int32_t* iters_out);
 
-/* Product q = H d with the Hessian at x (proj_mask projected). */
+/* Product q = H d [3 n_verts] with the assembled Hessian at x (Sec. 3; the
+ * elements of proj_mask projected as in Eq. (5)). */
 ppn_status ppn_hessian_product(ppn_scene* s, const double* x, const uint8_t* proj_mask,
                                const double* d, double* q_out);
 
-/* Psi(x + gamma_k dx) - Psi(x) for n_gamma step sizes (line search). */
+/* Psi(x + gamma_k dx) - Psi(x) for n_gamma step sizes (the backtracking line
+ * search of Sec. 5.1), evaluated term by term in FP64; out [n_gamma]. */
 ppn_status ppn_energy_difference(ppn_scene* s, const double* x, const double* dx, int32_t n_gamma,
                                  const double* gammas, double* out);
 
