@@ -23,8 +23,8 @@ Everything is single-threaded NumPy / SciPy in float64.  Every function is a
 plain definition or the algorithm's steps in the paper's order; no blocking or
 fusion beyond a loop over element chunks that only bounds memory.
 
-Readings of points the paper leaves open are collected in ``newton.PARAMS_DOC``
-and listed with their justification in the design document.
+Readings of points the paper leaves open are listed in the docstring of
+``newton`` and in the comments of the functions that implement them.
 """
 from .snh import lame_to_snh, psi, first_piola, d2psi_dF2
 from .fem import Mesh, element_psi, element_grad_hess, lumped_mass

@@ -13,8 +13,7 @@ Newton's method (Sec. 3, Eq. (1)): solve H^k dx^k = -g^k, then x <- x + gamma dx
   alpha |g|_inf the first time projection is needed, and everything is
   projected once delta <= eps_delta (Sec. 4, projection heuristic).
 
-Readings of points the paper leaves open (each also listed in the design
-document):
+Readings of points the paper leaves open:
 * delta and the PDN countdown are reset at the start of each time step;
   within a step delta carries over Newton iterations.
 * The Newton iterate starts at x^n; xhat = x^n + h v^n + h^2 g_grav; after the
