@@ -11,13 +11,14 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import (MODES, PPN_FP64, PPN_MIXED, PPN_PDN, PPN_PN, PPN_PPN, PPN_STOP_GRAD_REL,
-                   PPN_STOP_VEL, STATUS, ppn_engine_info, ppn_iter_record, ppn_params,
-                   ppn_scene_desc, ppn_step_stats)
+from ._abi import (MODES, PPN_FP64, PPN_MIXED, PPN_ORDER_MORTON, PPN_ORDER_PENCIL, PPN_PDN, PPN_PN,
+                   PPN_PPN, PPN_STOP_GRAD_REL, PPN_STOP_VEL, STATUS, ppn_engine_info, ppn_iter_record,
+                   ppn_params, ppn_scene_desc, ppn_step_stats)
 
-__all__ = ["Scene", "Engine", "PPNError", "ppn_params_default", "ppn_project_batch_dev", "ppn_params",
-           "ppn_step_stats", "ppn_iter_record", "MODES", "PPN_PN", "PPN_PDN", "PPN_PPN",
-           "PPN_FP64", "PPN_MIXED", "PPN_STOP_VEL", "PPN_STOP_GRAD_REL", "library_path"]
+__all__ = ["Scene", "Engine", "PPNError", "ppn_params_default", "ppn_project_batch_dev", "ppn_locality_order",
+           "ppn_params", "ppn_step_stats", "ppn_iter_record", "MODES", "PPN_PN", "PPN_PDN", "PPN_PPN",
+           "PPN_FP64", "PPN_MIXED", "PPN_STOP_VEL", "PPN_STOP_GRAD_REL", "PPN_ORDER_PENCIL",
+           "PPN_ORDER_MORTON", "library_path"]
 
 
 class PPNError(RuntimeError):
@@ -77,6 +78,18 @@ def ppn_project_batch_dev(H_dev, Hhat_dev, n, eps=1e-8, stream=None):
         return C.c_void_p(t.data_ptr() if hasattr(t, "data_ptr") else int(t))
     _check(_abi.lib().ppn_project_batch_dev(ptr(H_dev), ptr(Hhat_dev), int(n), float(eps),
                                            C.c_void_p(stream) if stream else None))
+
+
+def ppn_locality_order(rest_xyz, tets, kind="pencil"):
+    """(vertex_order, tet_order), new -> old ids of a numbering with spatial
+    locality; kind "pencil" (banded sweep) or "morton" (Z-order curve)."""
+    kind = {"pencil": PPN_ORDER_PENCIL, "morton": PPN_ORDER_MORTON}[kind]
+    X = _f64(rest_xyz).reshape(-1, 3)
+    tt = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+    vo = np.empty(X.shape[0], np.int32)
+    to = np.empty(tt.shape[0], np.int32)
+    _check(_abi.lib().ppn_locality_order(X.shape[0], _d(X), tt.shape[0], _i(tt), kind, _i(vo), _i(to)))
+    return vo, to
 
 
 class Scene:

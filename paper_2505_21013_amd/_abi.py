@@ -8,6 +8,7 @@ PPN_PN, PPN_PDN, PPN_PPN = 0, 1, 2
 MODES = {"PN": PPN_PN, "PDN": PPN_PDN, "PPN": PPN_PPN}
 PPN_FP64, PPN_MIXED = 0, 1
 PPN_STOP_VEL, PPN_STOP_GRAD_REL = 0, 1
+PPN_ORDER_PENCIL, PPN_ORDER_MORTON = 0, 1
 STATUS = {0: "PPN_OK", -1: "PPN_ERR_ARG", -2: "PPN_ERR_MESH", -3: "PPN_ERR_OOM", -4: "PPN_ERR_DEVICE",
           -5: "PPN_ERR_STATE", 1: "PPN_WARN_NOT_CONVERGED", 2: "PPN_WARN_LS_FAIL"}
 
@@ -101,6 +102,7 @@ SIGNATURES = {
     "ppn_hessian_product": (C.c_int, [P, dp, u8p, dp, dp]),
     "ppn_energy_difference": (C.c_int, [P, dp, dp, C.c_int32, dp, dp]),
     "ppn_project_batch_dev": (C.c_int, [P, P, C.c_int64, C.c_double, P]),
+    "ppn_locality_order": (C.c_int, [C.c_int32, dp, C.c_int32, ip, C.c_int32, ip, ip]),
     "ppn_engine_create": (C.c_int, [C.POINTER(P), C.c_int32, C.c_int64]),
     "ppn_engine_destroy": (C.c_int, [P]),
     "ppn_engine_add_scene": (C.c_int, [P, C.POINTER(ppn_scene_desc), ip]),

@@ -7,6 +7,7 @@
 #include "../../include/ppn.h"
 #include "engine.h"
 #include "scene.h"
+#include "topology.h"
 
 struct ppn_scene {
   ppn::Scene* impl = nullptr;
@@ -322,6 +323,25 @@ ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t 
   if (e != hipSuccess) {
     g_error = std::string("ppn_project_batch_dev: ") + hipGetErrorString(e);
     return PPN_ERR_DEVICE;
+  }
+  return PPN_OK;
+}
+
+ppn_status ppn_locality_order(int32_t n_verts, const double* rest_xyz, int32_t n_tets,
+                              const int32_t* tets, int32_t kind, int32_t* vertex_order,
+                              int32_t* tet_order) {
+  const char* null_name = !rest_xyz ? "rest_xyz" : !tets ? "tets" : !vertex_order ? "vertex_order"
+                          : !tet_order ? "tet_order" : nullptr;
+  if (null_name) return null_arg(nullptr, null_name);
+  try {
+    std::string err;
+    if (!ppn::locality_order(n_verts, rest_xyz, n_tets, tets, kind, vertex_order, tet_order, err)) {
+      g_error = err;
+      return PPN_ERR_MESH;
+    }
+  } catch (const std::bad_alloc&) {
+    g_error = "host allocation failed";
+    return PPN_ERR_OOM;
   }
   return PPN_OK;
 }

@@ -74,4 +74,16 @@ constexpr int kSell = 64;  // rows per sliced-ELL group (one wavefront)
 bool build_topology(int32_t n_verts, int32_t n_tets, const int32_t* tets, Topology& out,
                     std::string& err);
 
+// Vertex orders of locality_order.
+constexpr int32_t kOrderPencil = 0;  // banded sweep across the longest axis
+constexpr int32_t kOrderMorton = 1;  // Z-order curve of the rest positions
+
+// A numbering of the mesh with spatial locality: vertex_order[n_verts] and
+// tet_order[n_tets] list the input ids in their new order (new -> old), the
+// vertices in the order `kind` names, the elements by their new vertex ids.
+// Returns false and sets err for an empty mesh, an unknown kind, a
+// non-finite position or an index out of range.
+bool locality_order(int32_t n_verts, const double* X, int32_t n_tets, const int32_t* tets,
+                    int32_t kind, int32_t* vertex_order, int32_t* tet_order, std::string& err);
+
 }  // namespace ppn

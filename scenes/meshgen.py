@@ -244,6 +244,55 @@ def serving_scenes(n_scenes=128, seed=4, t_lo=1e3, t_hi=5e5, ramp_steps=20):
     return out
 
 
+# The twelve even permutations of a tetrahedron's four local vertices: each
+# keeps the orientation (the sign of the volume) of the element it reorders.
+_EVEN4 = [q for q in itertools.permutations(range(4))
+          if sum(q[i] > q[j] for i in range(4) for j in range(i + 1, 4)) % 2 == 0]
+
+
+def permuted(sc: Scene, vertex_order, tet_order, local=None, name=None) -> Scene:
+    """The same scene numbered anew: new vertex v is old vertex_order[v], new
+    element e is old element tet_order[e], and (if given) local[e] reorders
+    the new element's four vertices.  Geometry, materials and the boundary
+    schedule are carried along; the Dirichlet ids stay ascending, their
+    targets reordered with them.  The maps are kept in ``meta["vertex_of_new"]``
+    and ``meta["tet_of_new"]`` (composed with any the scene already had)."""
+    old_of_new = np.asarray(vertex_order, np.int64)
+    tet_of_new = np.asarray(tet_order, np.int64)
+    nv, nt = sc.n_verts, sc.n_tets
+    assert np.array_equal(np.sort(old_of_new), np.arange(nv)), "vertex_order is not a permutation"
+    assert np.array_equal(np.sort(tet_of_new), np.arange(nt)), "tet_order is not a permutation"
+    new_of_old = np.empty(nv, np.int64)
+    new_of_old[old_of_new] = np.arange(nv)
+    tets = new_of_old[sc.tets[tet_of_new]]
+    if local is not None:
+        tets = np.take_along_axis(tets, np.asarray(local, np.int64), axis=1)
+    ids = new_of_old[sc.dirichlet_ids]
+    order = np.argsort(ids, kind="stable")
+    src_targets = sc.targets
+    meta = dict(sc.meta)
+    meta["vertex_of_new"] = np.asarray(sc.meta.get("vertex_of_new", np.arange(nv)))[old_of_new]
+    meta["tet_of_new"] = np.asarray(sc.meta.get("tet_of_new", np.arange(nt)))[tet_of_new]
+    return Scene(name=name or f"{sc.name}_perm", X=sc.X[old_of_new].copy(), tets=tets.astype(np.int32),
+                 x0=sc.x0[old_of_new].copy(), v0=sc.v0[old_of_new].copy(),
+                 E=sc.E[tet_of_new].copy(), nu=sc.nu[tet_of_new].copy(), rho=sc.rho, dt=sc.dt,
+                 gravity=sc.gravity, dirichlet_ids=ids[order].astype(np.int32),
+                 targets=lambda step: np.asarray(src_targets(step))[order],
+                 n_steps=sc.n_steps, stop_mode=sc.stop_mode, stop_tol=sc.stop_tol, meta=meta)
+
+
+def renumbered(sc: Scene, seed: int = 0) -> Scene:
+    """The same scene with its vertices and elements numbered at random:
+    vertex ids permuted, the element list shuffled, and each element's local
+    vertices reordered by a random even permutation (which keeps its
+    orientation)."""
+    rng = np.random.default_rng(seed)
+    vo = rng.permutation(sc.n_verts)
+    to = rng.permutation(sc.n_tets)
+    local = np.array(_EVEN4, np.int64)[rng.integers(0, len(_EVEN4), sc.n_tets)]
+    return permuted(sc, vo, to, local, name=f"{sc.name}_renum{seed}")
+
+
 def config(k: int, **kw):
     """The workload configurations by index: 0 small parity cube, 1 twisted
     beam (122,880 tets), 2 compressed heterogeneous cube (1,572,864 tets),

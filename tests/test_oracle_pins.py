@@ -469,3 +469,33 @@ def test_ppn_projects_fewer_than_pdn_on_compression():
         _, st = run_scene(sc, mode)
         res[mode] = sum(s.projected for s in st)
     assert res["PPN"] < res["PDN"]
+
+
+# ---------------------------------------------------------------- P14: numbering invariance
+@pytest.mark.parametrize("mode", ["PN", "PDN", "PPN"])
+def test_P14_results_do_not_depend_on_the_numbering(mode):
+    """The method acts on the mesh, not on how its vertices and elements are
+    numbered: a randomly renumbered scene (vertices, element order and each
+    element's local order, orientation kept) takes the same Newton iterations
+    and projects the same elements, and its positions mapped back agree up to
+    the rounding of reordered sums.  An indexing slip (a transposed block, a
+    local vertex taken in the wrong order, a scatter through the wrong map)
+    breaks this on some numbering."""
+    from scenes import renumbered
+    sc = cube_compress(n=4, n_steps=4, ramp_steps=4)
+    rn = renumbered(sc, seed=7)
+    old, tmap = rn.meta["vertex_of_new"], rn.meta["tet_of_new"]
+    runs = {}
+    for s in (sc, rn):
+        xs = []
+        _, st = run_scene(s, mode, trace=True, callback=lambda n, S, _: xs.append(S.x.copy()))
+        runs[s.name] = (xs, st)
+    (xa, sa), (xb, sb) = runs[sc.name], runs[rn.name]
+    assert sum(s.projected for s in sa) > 0 or mode == "PN"
+    for a, b, ta, tb in zip(xa, xb, sa, sb):
+        assert (ta.newton_iters, ta.projected, ta.inner_rounds) == (tb.newton_iters, tb.projected, tb.inner_rounds)
+        assert np.max(np.abs(b - a[old])) <= 1e-12
+        for ra, rb in zip(ta.trace, tb.trace):
+            pa = ra.get("projected_idx", np.zeros(0, np.int32))
+            pb = rb.get("projected_idx", np.zeros(0, np.int32))
+            assert np.array_equal(np.sort(tmap[pb]), pa)

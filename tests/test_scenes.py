@@ -50,3 +50,27 @@ def test_seeded_and_schedules():
     r0 = t0[right, 1:] - 0.1
     r1 = t25[right, 1:] - 0.1
     assert np.allclose(r1, -r0)
+
+
+def test_renumbered_is_the_same_mesh():
+    """A renumbered scene holds the same elements (as vertex sets mapped back),
+    keeps every orientation, and carries materials, states and the boundary
+    schedule along with the new numbering."""
+    from scenes import cube_compress, renumbered
+    s = cube_compress(n=4, n_steps=6, ramp_steps=6)
+    r = renumbered(s, seed=7)
+    old, tmap = r.meta["vertex_of_new"], r.meta["tet_of_new"]
+    assert sorted(old.tolist()) == list(range(s.n_verts)) and sorted(tmap.tolist()) == list(range(s.n_tets))
+    assert not np.array_equal(old, np.arange(s.n_verts))
+    assert np.array_equal(np.sort(old[r.tets], axis=1), np.sort(s.tets[tmap], axis=1))
+    assert not np.array_equal(old[r.tets], s.tets[tmap])          # local orders changed too
+    D = np.stack([r.X[r.tets[:, a]] - r.X[r.tets[:, 0]] for a in (1, 2, 3)], axis=-1)
+    D0 = np.stack([s.X[s.tets[tmap, a]] - s.X[s.tets[tmap, 0]] for a in (1, 2, 3)], axis=-1)
+    assert np.allclose(np.linalg.det(D), np.linalg.det(D0), rtol=1e-12, atol=0)
+    assert np.array_equal(r.X, s.X[old]) and np.array_equal(r.x0, s.x0[old])
+    assert np.array_equal(r.E, s.E[tmap]) and np.array_equal(r.nu, s.nu[tmap])
+    assert np.all(np.diff(r.dirichlet_ids) > 0)
+    for n in (0, 3, 6):
+        got = dict(zip(old[r.dirichlet_ids].tolist(), map(tuple, r.targets(n))))
+        want = dict(zip(s.dirichlet_ids.tolist(), map(tuple, s.targets(n))))
+        assert got == want
