@@ -141,11 +141,12 @@ __host__ __device__ inline size_t value_index(int32_t pos, int e) {
 // Bytes of the FP64 sliced-ELL values (9 entries of 64 rows per slot).
 inline int64_t matrix_bytes(const Dev& D) { return D.n_slots * 9 * 64 * int64_t(sizeof(double)); }
 
-// The PCG product streams an FP64 matrix larger than this with non-temporal
-// loads; a smaller one is read with ordinary loads and stays resident in the
-// 256 MB last-level cache between iterations (measured per PCG iteration,
-// cached against streamed: 23 / 26 us at 32^3 cells, 37 / 41 us at 48^3,
-// 52 / 59 us at 56^3 with its 200 MB matrix; 101 / 91 us at 64^3, 297 MB).
+// The PCG product streams a matrix (FP64, or the FP32 copy) whose values take
+// more than this with non-temporal loads; a smaller one is read with ordinary
+// loads and stays resident in the 256 MB last-level cache between iterations
+// (measured per PCG iteration in FP64, cached against streamed: 23 / 26 us at
+// 32^3 cells, 37 / 41 us at 48^3, 52 / 59 us at 56^3 with its 200 MB matrix;
+// 101 / 91 us at 64^3, 297 MB).
 constexpr int64_t kCacheResidentMatrixBytes = int64_t(224) << 20;
 inline bool stream_matrix(int64_t bytes) { return bytes > kCacheResidentMatrixBytes; }
 
@@ -199,7 +200,8 @@ void launch_pcg_batch_init(const PcgJob<double>* jobs, int n, int total_wg, hipS
 void launch_pcg_batch_init(const PcgJob<float>* jobs, int n, int total_wg, hipStream_t st);
 // any_first: some job starts at this iteration (its first product is a
 // separate instance, launched only then).  matrix_bytes: the jobs' summed
-// FP64 matrix size (selects streaming or cache-resident loads).
+// FP64 matrix size (selects streaming or cache-resident loads; an FP32 copy
+// takes half of it).
 void launch_pcg_batch_iter(const PcgJob<double>* jobs, int n, int total_wg, int j, bool any_first,
                            int64_t matrix_bytes, hipStream_t st);
 void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j, bool any_first,

@@ -135,10 +135,11 @@ __device__ __forceinline__ void load_block(const double* __restrict__ vals, int 
 }
 // FP32: entries paired, pair k = (2k, 2k+1) as a float2 at slot*576 + 2*(64k + lane)
 // for k < 4, entry 8 at slot*576 + 512 + lane: five loads of 512 / 256 bytes.
-// The FP32 matrix (~160 MB with its column indices) fits in the 256 MB
-// last-level cache, so ordinary loads let it stay resident from one
-// iteration to the next (measured: 62 against 74 us per PCG iteration with
-// non-temporal loads on the 1.57M-tet cube).
+// An FP32 matrix within the cache-resident size (148 MB of values on the
+// 1.57M-tet cube) is read with ordinary loads and stays in the 256 MB
+// last-level cache from one iteration to the next (measured there: 62 against
+// 74 us per PCG iteration with non-temporal loads); a larger one is streamed
+// with non-temporal loads like the FP64 matrix.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <bool kStream>
 __device__ __forceinline__ void load_block(const float* __restrict__ vals, int slot, int l,
@@ -147,11 +148,11 @@ __device__ __forceinline__ void load_block(const float* __restrict__ vals, int s
   const f32x2* v2 = reinterpret_cast<const f32x2*>(base) + l;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const f32x2 p = v2[k * kSell];
+    const f32x2 p = kStream ? __builtin_nontemporal_load(v2 + k * kSell) : v2[k * kSell];
     w[2 * k] = p.x;
     w[2 * k + 1] = p.y;
   }
-  w[8] = base[8 * kSell + l];
+  w[8] = kStream ? __builtin_nontemporal_load(base + 8 * kSell + l) : base[8 * kSell + l];
 }
 
 // q_i = sum over the row's slots of B d_col, d read from a plain [N][3] vector (FP64).
@@ -408,10 +409,10 @@ static void pcg_iter_k(const Dev& D, const PcgVec<T>& V, int j, double tol2, int
   k_pcg_update<T, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
 }
 
-// The FP32 matrix of the mixed form always fits in the last-level cache.
+// fp64_bytes: the FP64 matrix size; the FP32 copy of the mixed form takes half.
 template <typename T>
-static bool streamed(int64_t matrix_bytes) {
-  return sizeof(T) == 8 && stream_matrix(matrix_bytes);
+static bool streamed(int64_t fp64_bytes) {
+  return stream_matrix(sizeof(T) == 8 ? fp64_bytes : fp64_bytes / 2);
 }
 
 template <typename T>
