@@ -285,10 +285,11 @@ ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t 
  * rest positions rest_xyz [n_verts][3] and tets [n_tets][4].  Vertex orders:
  *  PPN_ORDER_PENCIL: a banded sweep.  The axes are ranked by the mesh's
  *    extent, longest first; coordinates along the first two are rounded to
- *    the mesh spacing (the 10th percentile of the element edge lengths) and
- *    vertices sorted by them, then by the exact coordinate along the shortest
- *    axis.  On a regular grid this is the lexicographic numbering with the
- *    shortest axis fastest.
+ *    the mesh spacing (the 10th percentile of the element edge lengths over
+ *    a fixed-stride sample of at most 2^20 elements) and vertices sorted by
+ *    them, then by the exact coordinate along the shortest axis.  On a
+ *    regular grid this is the lexicographic numbering with the shortest axis
+ *    fastest.
  *  PPN_ORDER_MORTON: the Z-order curve of the rest positions (21 bits per
  *    axis over the bounding box); adapts to graded meshes, with longer jumps.
  * Elements are sorted by their four new vertex ids (ascending, compared

@@ -5,7 +5,7 @@
 //  * pencil: the axes ranked by the mesh's extent along them, longest first
 //    (ties by axis index); rest coordinates along the first two rounded to
 //    multiples of the mesh spacing h (the 10th percentile of the edge
-//    lengths); vertices sorted by those two and then by the exact coordinate
+//    lengths, over a fixed-stride sample of at most 2^20 elements); vertices sorted by those two and then by the exact coordinate
 //    along the shortest axis.  Neighbours then lie within one slab across the
 //    longest axis, the narrowest band a sweep can give, in runs of ids along
 //    the shortest one, which keeps the column gathers of the matrix product
@@ -101,15 +101,19 @@ bool locality_order(int32_t N, const double* X, int32_t T, const int32_t* tets, 
                      [&](int32_t a, int32_t b) { return key[a] < key[b]; });
   } else {
     // Mesh spacing: the 10th percentile of the element edge lengths (every
-    // edge counted once per element that holds it).
-    std::vector<double> len(int64_t(T) * 6);
-    for (int64_t e = 0; e < T; ++e)
+    // edge counted once per element that holds it), over at most 2^20
+    // elements taken at a fixed stride.
+    const int64_t ns = std::min<int64_t>(T, int64_t(1) << 20);
+    std::vector<double> len(ns * 6);
+    for (int64_t k = 0; k < ns; ++k) {
+      const int64_t e = k * T / ns;
       for (int p = 0; p < 6; ++p) {
         const double* a = X + 3 * int64_t(tets[4 * e + kPairA[p]]);
         const double* b = X + 3 * int64_t(tets[4 * e + kPairC[p]]);
-        len[6 * e + p] = std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) +
+        len[6 * k + p] = std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) +
                                    (a[2] - b[2]) * (a[2] - b[2]));
       }
+    }
     auto nth = len.begin() + len.size() / 10;
     std::nth_element(len.begin(), nth, len.end());
     double h = *nth;
