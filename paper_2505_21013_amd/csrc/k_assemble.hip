@@ -13,6 +13,8 @@
 // when delta <= eps_delta (fallback to PN).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "k_common.h"
 #include "topology.h"
 
@@ -127,16 +129,37 @@ __global__ __launch_bounds__(kBlock) void k_assemble_vertex(Dev D) {
   }
 }
 
-// Edge pass: off-diagonal block (lo, hi) and its transpose (hi, lo).
-__global__ __launch_bounds__(kBlock) void k_assemble_edge(Dev D) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= D.E) return;
-  gather_edge(D, k);
+// Edge pass: off-diagonal block (lo, hi) and its transpose (hi, lo).  Like
+// the vertex pass it is component-parallel: thread (k, c) of a workgroup's
+// kEChunk edges sums entry c of edge k's slots in ascending slot order (the
+// order of gather_edge, so the same bits) and stores it in both blocks.  The
+// threads of a wavefront read consecutive doubles of their edges' contiguous
+// slot range, where one lane per edge would walk its own 72-byte records and
+// fetch each cache line several times.  One chunk per workgroup, mapped so
+// that each XCD owns a contiguous range of edges: the chunks in flight on an
+// XCD are one narrow window, whose scattered block writes fill whole lines
+// while they are in that XCD's L2.
+constexpr int kEBlock = 1024;
+constexpr int kEChunk = kEBlock / 9;  // 113 edges (1017 threads) per workgroup
+__global__ __launch_bounds__(kEBlock) void k_assemble_edge(Dev D, int n_wg) {
+  const int vl = threadIdx.x / 9, c = threadIdx.x % 9;
+  const int64_t k = int64_t(logical_wg(n_wg)) * kEChunk + vl;
+  if (vl >= kEChunk || k >= D.E) return;
+  double s = 0.0;
+#pragma unroll 4
+  for (int t = D.eptr[k]; t < D.eptr[k + 1]; ++t) s += D.eslots[size_t(t) * 9 + c];
+  const int r = c / 3, cc = c % 3;
+  D.vals[value_index(D.eblk_up[k], c)] = s;
+  D.vals[value_index(D.eblk_lo[k], 3 * cc + r)] = s;
 }
 
 void launch_assemble_full(const Dev& D, hipStream_t st) {
   k_assemble_vertex<<<D.G, kBlock, 0, st>>>(D);
-  if (D.E > 0) k_assemble_edge<<<(D.E + kBlock - 1) / kBlock, kBlock, 0, st>>>(D);
+  if (D.E > 0) {
+    // logical_wg needs a multiple of 8 workgroups; the extra ones exit at once.
+    const int n_wg = int(((int64_t(D.E) + kEChunk - 1) / kEChunk + 7) / 8 * 8);
+    k_assemble_edge<<<n_wg, kEBlock, 0, st>>>(D, n_wg);
+  }
 }
 
 // Re-gather the 10 blocks of each listed (just projected) element.  Blocks
