@@ -271,7 +271,7 @@ def run_serve(a):
         print(f"warm: {info0}", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         due = t0
-        reqs = []
+        reqs, tags = [], []
         for g, k in zip(gaps, which):
             due += g
             now = time.perf_counter()
@@ -279,6 +279,7 @@ def run_serve(a):
                 time.sleep(due - now)
             step[k] += 1
             reqs.append(e.ppn_engine_submit(ids[k], "PPN", scenes[k].targets(step[k])))
+            tags.append((scenes[k].name, int(scenes[k].n_tets), step[k]))
         res = [e.ppn_engine_wait(r) for r in reqs]
         el = time.perf_counter() - t0
         info = e.ppn_engine_get_info()
@@ -297,6 +298,9 @@ def run_serve(a):
             "p50_queue_ms": float(np.percentile(que, 50)), "p99_queue_ms": float(np.percentile(que, 99)),
             "all_ok": all(r["status"] in ("PPN_OK", "PPN_WARN_NOT_CONVERGED") for r in res),
             "not_converged": sum(r["status"] != "PPN_OK" for r in res),
+            "not_converged_requests": [{"scene": t[0], "tets": t[1], "step": t[2], "status": r["status"],
+                                        "newton_iters": r["newton_iters"]}
+                                       for t, r in zip(tags, res) if r["status"] != "PPN_OK"],
             "resident_bytes": info["resident_bytes"], "resident_scenes": info["resident_scenes"],
             "evictions": info["evictions"]}
 

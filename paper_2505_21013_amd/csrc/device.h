@@ -141,14 +141,28 @@ __host__ __device__ inline size_t value_index(int32_t pos, int e) {
 // Bytes of the FP64 sliced-ELL values (9 entries of 64 rows per slot).
 inline int64_t matrix_bytes(const Dev& D) { return D.n_slots * 9 * 64 * int64_t(sizeof(double)); }
 
-// The PCG product streams a matrix (FP64, or the FP32 copy) whose values take
-// more than this with non-temporal loads; a smaller one is read with ordinary
-// loads and stays resident in the 256 MB last-level cache between iterations
-// (measured per PCG iteration in FP64, cached against streamed: 23 / 26 us at
-// 32^3 cells, 37 / 41 us at 48^3, 52 / 59 us at 56^3 with its 200 MB matrix;
-// 101 / 91 us at 64^3, 297 MB).
+// Load modes of the PCG product, chosen per launch from the size of the matrix
+// values (FP64, or the FP32 copy; summed over the jobs of a batched launch).
+// None changes the arithmetic or its order.
+//  * kLoadStream, above 224 MB: non-temporal loads, streamed from HBM so that
+//    the matrix does not evict the gathered vectors (measured per PCG
+//    iteration in FP64, cached against streamed: 23 / 26 us at 32^3 cells,
+//    37 / 41 us at 48^3, 52 / 59 us at 56^3 with its 200 MB matrix; 101 / 91 us
+//    at 64^3, 297 MB).
+//  * kLoadCached: ordinary loads; the matrix stays resident in the 256 MB
+//    last-level cache between iterations.
+//  * kLoadSmall, up to 64 MB: as kLoadCached with two slots in flight per lane
+//    in the FP64 product: few workgroups, bound by load latency (product
+//    13.7 -> 12.5 us on the 122,880-tet beam, 15.3 -> 14.2 us at 32^3; one
+//    slot stays faster at 48^3 and 56^3, 25.2 / 25.8 and 37.0 / 38.0 us).
+constexpr int kLoadSmall = 0, kLoadCached = 1, kLoadStream = 2;
+constexpr int64_t kSmallMatrixBytes = int64_t(64) << 20;
 constexpr int64_t kCacheResidentMatrixBytes = int64_t(224) << 20;
-inline bool stream_matrix(int64_t bytes) { return bytes > kCacheResidentMatrixBytes; }
+inline int load_mode(int64_t bytes) {
+  return bytes > kCacheResidentMatrixBytes ? kLoadStream
+         : bytes > kSmallMatrixBytes       ? kLoadCached
+                                           : kLoadSmall;
+}
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
 void launch_precompute(const Dev& D, double rho, hipStream_t st);
@@ -200,8 +214,7 @@ void launch_pcg_batch_init(const PcgJob<double>* jobs, int n, int total_wg, hipS
 void launch_pcg_batch_init(const PcgJob<float>* jobs, int n, int total_wg, hipStream_t st);
 // any_first: some job starts at this iteration (its first product is a
 // separate instance, launched only then).  matrix_bytes: the jobs' summed
-// FP64 matrix size (selects streaming or cache-resident loads; an FP32 copy
-// takes half of it).
+// FP64 matrix size (selects the load mode; an FP32 copy takes half of it).
 void launch_pcg_batch_iter(const PcgJob<double>* jobs, int n, int total_wg, int j, bool any_first,
                            int64_t matrix_bytes, hipStream_t st);
 void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j, bool any_first,

@@ -113,25 +113,26 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, cons
 // FP64: entries paired, pair k = (2k, 2k+1) at slot*576 + 128k + 2*lane, entry 8
 // at slot*576 + 512 + lane: four 16-byte loads (1024-byte runs over the
 // wavefront) and one 8-byte load.
-// kStream: the matrix is larger than the last-level cache (~300 MB at 1.57M
-// tets) and is streamed with non-temporal loads that keep it from evicting the
-// gathered (z, d) records.  Smaller matrices are read with ordinary loads and
-// stay cache-resident from one iteration to the next (measured: 21 against
-// 25 us per PCG iteration on the 122,880-tet beam; 101 against 91 us on the
-// 1.57M-tet cube the other way round).  The choice changes no arithmetic.
+// kLoad == kLoadStream: the matrix is larger than the last-level cache (~300 MB
+// at 1.57M tets) and is streamed with non-temporal loads that keep it from
+// evicting the gathered (z, d) records.  Smaller matrices are read with
+// ordinary loads and stay cache-resident from one iteration to the next
+// (measured: 21 against 25 us per PCG iteration on the 122,880-tet beam; 101
+// against 91 us on the 1.57M-tet cube the other way round).  The choice
+// changes no arithmetic.
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <bool kStream>
+template <int kLoad>
 __device__ __forceinline__ void load_block(const double* __restrict__ vals, int slot, int l,
                                            double w[9]) {
   const double* base = vals + size_t(slot) * (9 * kSell);
   const f64x2* v2 = reinterpret_cast<const f64x2*>(base) + l;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const f64x2 p = kStream ? __builtin_nontemporal_load(v2 + k * kSell) : v2[k * kSell];
+    const f64x2 p = kLoad == kLoadStream ? __builtin_nontemporal_load(v2 + k * kSell) : v2[k * kSell];
     w[2 * k] = p.x;
     w[2 * k + 1] = p.y;
   }
-  w[8] = kStream ? __builtin_nontemporal_load(base + 8 * kSell + l) : base[8 * kSell + l];
+  w[8] = kLoad == kLoadStream ? __builtin_nontemporal_load(base + 8 * kSell + l) : base[8 * kSell + l];
 }
 // FP32: entries paired, pair k = (2k, 2k+1) as a float2 at slot*576 + 2*(64k + lane)
 // for k < 4, entry 8 at slot*576 + 512 + lane: five loads of 512 / 256 bytes.
@@ -141,18 +142,18 @@ __device__ __forceinline__ void load_block(const double* __restrict__ vals, int 
 // 74 us per PCG iteration with non-temporal loads); a larger one is streamed
 // with non-temporal loads like the FP64 matrix.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-template <bool kStream>
+template <int kLoad>
 __device__ __forceinline__ void load_block(const float* __restrict__ vals, int slot, int l,
                                            float w[9]) {
   const float* base = vals + size_t(slot) * (9 * kSell);
   const f32x2* v2 = reinterpret_cast<const f32x2*>(base) + l;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const f32x2 p = kStream ? __builtin_nontemporal_load(v2 + k * kSell) : v2[k * kSell];
+    const f32x2 p = kLoad == kLoadStream ? __builtin_nontemporal_load(v2 + k * kSell) : v2[k * kSell];
     w[2 * k] = p.x;
     w[2 * k + 1] = p.y;
   }
-  w[8] = kStream ? __builtin_nontemporal_load(base + 8 * kSell + l) : base[8 * kSell + l];
+  w[8] = kLoad == kLoadStream ? __builtin_nontemporal_load(base + 8 * kSell + l) : base[8 * kSell + l];
 }
 
 // q_i = sum over the row's slots of B d_col, d read from a plain [N][3] vector (FP64).
@@ -167,7 +168,7 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
     const int c = D.col[slot * kSell + l];
     const double d0 = src[3 * c], d1 = src[3 * c + 1], d2 = src[3 * c + 2];
     double v[9];
-    load_block<false>(D.vals, slot, l, v);
+    load_block<kLoadCached>(D.vals, slot, l, v);
     q0 += v[0] * d0 + v[1] * d1 + v[2] * d2;
     q1 += v[3] * d0 + v[4] * d1 + v[5] * d2;
     q2 += v[6] * d0 + v[7] * d1 + v[8] * d2;
@@ -178,15 +179,16 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
 // so that q = H (z + beta d_old) = qz + beta qd needs beta only at the end.
 // The arithmetic and the accumulation are in the matrix type M (FP32 for the
 // FP32 matrix: the gathered FP64 vectors are rounded on load).
-template <typename M, bool kStream>
+template <typename M, int kLoad>
 __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __restrict__ vals,
                                                        const double* __restrict__ zd, bool with_d,
                                                        int g, int l, M qz[3], M qd[3]) {
   const int S = D.gslots[g];
   qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = M(0);
-  // FP64 streams from HBM and runs best with one slot in flight per lane; the
-  // cache-resident FP32 matrix gains from two (measured on the 1.57M-tet cube).
-  constexpr int kUnroll = sizeof(M) == 4 ? 2 : 1;
+  // FP64 runs best with one slot in flight per lane, streamed from HBM or from
+  // a cache-resident matrix above 64 MB, and with two for small matrices; the
+  // FP32 matrix gains from two (measured on the 1.57M-tet cube).
+  constexpr int kUnroll = sizeof(M) == 4 || kLoad == kLoadSmall ? 2 : 1;
 #pragma unroll kUnroll
   for (int s = 0; s < S; ++s) {
     const int slot = s * D.n_groups + g;
@@ -195,7 +197,7 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
     const double2 a = p[0], b = p[1];
     const M z0 = M(a.x), z1 = M(a.y), z2 = M(b.x);
     M w[9];
-    load_block<kStream>(vals, slot, l, w);
+    load_block<kLoad>(vals, slot, l, w);
     qz[0] += w[0] * z0 + w[1] * z1 + w[2] * z2;
     qz[1] += w[3] * z0 + w[4] * z1 + w[5] * z2;
     qz[2] += w[6] * z0 + w[7] * z1 + w[8] * z2;
@@ -216,7 +218,7 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
 // the batched kernels too, so that they compile to the same arithmetic as the
 // single-scene kernels (a runtime flag changes which products the compiler
 // fuses into FMAs, and with it the last bits).
-template <typename M, bool kFirst, bool kStream>
+template <typename M, bool kFirst, int kLoad>
 __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, int j, double tol2,
                                               int maxit, int w) {
   __shared__ double lds[16];
@@ -235,7 +237,7 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   const int i = w * kPcgBlock + threadIdx.x;
   const int g = i / kSell, l = i % kSell;
   M qz[3] = {0, 0, 0}, qd[3] = {0, 0, 0};
-  if (g < D.n_groups) sell_row_product_split<M, kStream>(D, V.vals, zcur, !kFirst, g, l, qz, qd);
+  if (g < D.n_groups) sell_row_product_split<M, kLoad>(D, V.vals, zcur, !kFirst, g, l, qz, qd);
 
   sa = wave_sum(sa);
   sb = wave_sum(sb);
@@ -299,10 +301,10 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   if (threadIdx.x == 0) D.part[kPartKappa * Gp + w] = kap;
 }
 
-template <typename M, bool kFirst, bool kStream>
+template <typename M, bool kFirst, int kLoad>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int j, double tol2,
                                                         int maxit) {
-  pcg_spmv_body<M, kFirst, kStream>(D, V, j, tol2, maxit, logical_wg(D.Gp));
+  pcg_spmv_body<M, kFirst, kLoad>(D, V, j, tol2, maxit, logical_wg(D.Gp));
 }
 
 // The row's inputs are loaded before the d^T q partials are combined, so both
@@ -391,37 +393,38 @@ static void pcg_init(const Dev& D, const PcgVec<T>& V, const double* src, double
 // A sampled product (events given) is launched with the events attached to the
 // launch itself, so that their interval is the kernel's execution and not the
 // dispatch gap after the preceding kernel.
-template <typename T, bool kStream>
+template <typename T, int kLoad>
 static void pcg_iter_k(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                        hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
   if (ev_spmv_start && ev_spmv_stop) {
     if (j == 0)
-      hipExtLaunchKernelGGL(k_pcg_spmv<T, true, kStream>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
+      hipExtLaunchKernelGGL(k_pcg_spmv<T, true, kLoad>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
                             ev_spmv_start, ev_spmv_stop, 0, D, V, j, tol2, maxit);
     else
-      hipExtLaunchKernelGGL(k_pcg_spmv<T, false, kStream>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
+      hipExtLaunchKernelGGL(k_pcg_spmv<T, false, kLoad>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
                             ev_spmv_start, ev_spmv_stop, 0, D, V, j, tol2, maxit);
   } else if (j == 0) {
-    k_pcg_spmv<T, true, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
+    k_pcg_spmv<T, true, kLoad><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
   } else {
-    k_pcg_spmv<T, false, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
+    k_pcg_spmv<T, false, kLoad><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
   }
-  k_pcg_update<T, kStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
+  k_pcg_update<T, kLoad == kLoadStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
 }
 
 // fp64_bytes: the FP64 matrix size; the FP32 copy of the mixed form takes half.
 template <typename T>
-static bool streamed(int64_t fp64_bytes) {
-  return stream_matrix(sizeof(T) == 8 ? fp64_bytes : fp64_bytes / 2);
+static int load_mode_of(int64_t fp64_bytes) {
+  return load_mode(sizeof(T) == 8 ? fp64_bytes : fp64_bytes / 2);
 }
 
 template <typename T>
 static void pcg_iter(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                      hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
-  if (streamed<T>(matrix_bytes(D)))
-    pcg_iter_k<T, true>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
-  else
-    pcg_iter_k<T, false>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
+  switch (load_mode_of<T>(matrix_bytes(D))) {
+    case kLoadStream: pcg_iter_k<T, kLoadStream>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop); break;
+    case kLoadCached: pcg_iter_k<T, kLoadCached>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop); break;
+    default: pcg_iter_k<T, kLoadSmall>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
+  }
 }
 
 void launch_pcg_init(const Dev& D, const PcgVec<double>& V, const double* src, double sign,
@@ -586,14 +589,14 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init_batch(const PcgJob<M>* _
 
 // Iteration jg of the batch is iteration jg - j0 of each job's own solve.  The
 // kFirst instance serves the jobs at their first iteration, the other the rest.
-template <typename M, bool kFirst, bool kStream>
+template <typename M, bool kFirst, int kLoad>
 __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv_batch(const PcgJob<M>* __restrict__ jobs, int n,
                                                               int jg) {
   int w;
   const PcgJob<M>& J = find_job(jobs, n, w);
   const int j = jg - J.j0;
   if ((j == 0) != kFirst) return;
-  pcg_spmv_body<M, kFirst, kStream>(J.D, J.V, j, J.tol2, J.maxit, w);
+  pcg_spmv_body<M, kFirst, kLoad>(J.D, J.V, j, J.tol2, J.maxit, w);
 }
 
 template <typename M, bool kStream>
@@ -615,21 +618,22 @@ template <typename M>
 static void batch_init(const PcgJob<M>* jobs, int n, int total_wg, hipStream_t st) {
   k_pcg_init_batch<M><<<total_wg, kPcgBlock, 0, st>>>(jobs, n);
 }
-template <typename M, bool kStream>
+template <typename M, int kLoad>
 static void batch_iter_k(const PcgJob<M>* jobs, int n, int total_wg, int j, bool any_first,
                          hipStream_t st) {
-  if (any_first) k_pcg_spmv_batch<M, true, kStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
-  k_pcg_spmv_batch<M, false, kStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
-  k_pcg_update_batch<M, kStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+  if (any_first) k_pcg_spmv_batch<M, true, kLoad><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+  k_pcg_spmv_batch<M, false, kLoad><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
+  k_pcg_update_batch<M, kLoad == kLoadStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
 }
 // matrix_bytes: the summed matrix size of the jobs (they share the cache).
 template <typename M>
 static void batch_iter(const PcgJob<M>* jobs, int n, int total_wg, int j, bool any_first,
                        int64_t matrix_bytes, hipStream_t st) {
-  if (streamed<M>(matrix_bytes))
-    batch_iter_k<M, true>(jobs, n, total_wg, j, any_first, st);
-  else
-    batch_iter_k<M, false>(jobs, n, total_wg, j, any_first, st);
+  switch (load_mode_of<M>(matrix_bytes)) {
+    case kLoadStream: batch_iter_k<M, kLoadStream>(jobs, n, total_wg, j, any_first, st); break;
+    case kLoadCached: batch_iter_k<M, kLoadCached>(jobs, n, total_wg, j, any_first, st); break;
+    default: batch_iter_k<M, kLoadSmall>(jobs, n, total_wg, j, any_first, st);
+  }
 }
 template <typename M>
 static void batch_gather(const PcgJob<M>* jobs, int n, PcgState* out, hipStream_t st) {
