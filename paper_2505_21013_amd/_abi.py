@@ -18,7 +18,8 @@ class ppn_params(C.Structure):
                 ("eps_clamp", C.c_double), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
                 ("pdn_countdown", C.c_int32), ("stop_mode", C.c_int32), ("newton_maxit", C.c_int32),
                 ("stop_tol", C.c_double), ("armijo_c", C.c_double), ("ls_maxit", C.c_int32),
-                ("eig_mirror", C.c_int32), ("k_dirichlet", C.c_double)]
+                ("eig_mirror", C.c_int32), ("k_dirichlet", C.c_double), ("pcg_load_mode", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ppn_step_stats(C.Structure):

@@ -420,7 +420,7 @@ static int load_mode_of(int64_t fp64_bytes) {
 template <typename T>
 static void pcg_iter(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                      hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
-  switch (load_mode_of<T>(matrix_bytes(D))) {
+  switch (D.pcg_load >= 0 ? D.pcg_load : load_mode_of<T>(matrix_bytes(D))) {
     case kLoadStream: pcg_iter_k<T, kLoadStream>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop); break;
     case kLoadCached: pcg_iter_k<T, kLoadCached>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop); break;
     default: pcg_iter_k<T, kLoadSmall>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);

@@ -75,6 +75,7 @@ void params_defaults(ppn_params* p) {
   p->armijo_c = 1e-4;
   p->ls_maxit = 30;
   p->k_dirichlet = 1e8;
+  p->pcg_load_mode = -1;
 }
 
 Scene::Scene(hipStream_t stream, bool own, int precision)
@@ -244,6 +245,7 @@ void Scene::load_mesh(Topology&& t, const double* rest, const int32_t* tets, con
     geometry(D, topo_);
     D.h = D_.h;
     D.k_dir = prm_.k_dirichlet;
+    D.pcg_load = prm_.pcg_load_mode;
     std::memcpy(D.grav, D_.grav, sizeof(D.grav));
     D_ = D;
     const size_t n = size_t(N), m = size_t(T);
@@ -381,8 +383,10 @@ void Scene::set_params(const ppn_params& p) {
   if (!(p.armijo_c > 0.0 && p.armijo_c < 1.0)) fail("armijo_c must be in (0, 1)");
   if (!(p.k_dirichlet >= 0.0)) fail("k_dirichlet must be >= 0");
   if (p.eig_mirror != 0 && p.eig_mirror != 1) fail("eig_mirror must be 0 or 1");
+  if (p.pcg_load_mode < -1 || p.pcg_load_mode > 2) fail("pcg_load_mode must be -1, 0, 1 or 2");
   prm_ = p;
   D_.k_dir = p.k_dirichlet;
+  D_.pcg_load = p.pcg_load_mode;
 }
 
 // ---------------------------------------------------------------- building blocks

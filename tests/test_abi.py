@@ -33,8 +33,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     from paper_2505_21013_amd import _abi
-    # ppn_params: 5 doubles, 4 int32, 2 doubles, 2 int32, 1 double = 88 bytes
-    assert ctypes.sizeof(_abi.ppn_params) == 5 * 8 + 4 * 4 + 2 * 8 + 2 * 4 + 8
+    # ppn_params: 5 doubles, 4 int32, 2 doubles, 2 int32, 1 double, 2 int32 = 96 bytes
+    assert ctypes.sizeof(_abi.ppn_params) == 5 * 8 + 4 * 4 + 2 * 8 + 2 * 4 + 8 + 2 * 4
     assert ctypes.sizeof(_abi.ppn_step_stats) == 10 * 4 + 8 + 7 * 8 + 8 + 2 * 4
     assert ctypes.sizeof(_abi.ppn_iter_record) == 6 * 4 + 6 * 8
 

@@ -6,7 +6,10 @@
 * iteration caps of 1, 2, 3, 5 and 17 on an SPD system (every element
   projected) that converges in 12: the solve stops at the cap, or converges
   below it, with the oracle's count and iterate;
-* a loose tolerance, met after a few iterations: the same count and iterate.
+* a loose tolerance, met after a few iterations: the same count and iterate;
+* the product's load modes (small, cache-resident, streamed; normally chosen
+  from the matrix size), each forced on one scene: the same bits in every
+  mode, for one solve and for whole steps, in FP64 and the mixed form.
 
 These counts are small and irregular, so the launches that the host enqueues
 past the device's stop decision (which return at once) are a large part of
@@ -18,6 +21,7 @@ import pytest
 from oracle.assemble import diagonal_blocks
 from oracle.pcg import pcg_block_jacobi
 from oracle.project import project_to_pd
+from paper_2505_21013_amd import PPN_FP64, PPN_MIXED, PPNError, run_steps
 from scenes import cube_compress
 
 from helpers import gpu_scene, oracle_stepper, squashed_state
@@ -78,3 +82,31 @@ def test_loose_tolerance_meets_it_in_few_iterations():
     assert it == ito
     assert np.linalg.norm(dx - dxo) <= 1e-9 * np.linalg.norm(dxo)
     assert np.linalg.norm(Ho @ dx + grad) <= 0.3 * np.linalg.norm(grad) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("precision", [PPN_FP64, PPN_MIXED])
+def test_every_load_mode_gives_the_same_bits(precision):
+    sc = _scene()
+    x = squashed_state(sc, seed=6)
+    mask = np.ones(sc.n_tets, np.uint8)
+    solves, steps = [], []
+    for mode in (-1, 0, 1, 2):
+        g = gpu_scene(sc, precision=precision, pcg_load_mode=mode)
+        solves.append(g.ppn_solve(x, proj_mask=mask))
+        g.close()
+        g = gpu_scene(sc, precision=precision, pcg_load_mode=mode)
+        st = run_steps(g, sc, "PPN", 3)
+        steps.append(([(t["newton_iters"], t["pcg_iters"], t["projected"]) for t in st], g.ppn_get_positions()))
+        g.close()
+    dx0, ind0, it0 = solves[0]
+    assert not ind0 and it0 > 0
+    for dx, ind, it in solves[1:]:
+        assert (ind, it) == (ind0, it0) and np.array_equal(dx, dx0)
+    assert sum(c[1] for c in steps[0][0]) > 0
+    for counts, xs in steps[1:]:
+        assert counts == steps[0][0] and np.array_equal(xs, steps[0][1])
+
+
+def test_load_mode_out_of_range_is_refused():
+    with pytest.raises(PPNError, match="pcg_load_mode"):
+        gpu_scene(_scene(), pcg_load_mode=3)
