@@ -119,6 +119,8 @@ bool locality_order(int32_t N, const double* X, int32_t T, const int32_t* tets, 
     double h = *nth;
     double extent = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
     if (!(h > 0.0)) h = extent > 0.0 ? extent / std::cbrt(double(N)) : 1.0;
+    // Rounded coordinates stay below 2^40 (far inside int64) whatever the edges.
+    h = std::max(h, extent * 0x1p-40);
     int ax[3] = {0, 1, 2};
     std::stable_sort(ax, ax + 3, [&](int a, int b) { return hi[a] - lo[a] > hi[b] - lo[b]; });
     std::vector<int64_t> q0(N), q1(N);
