@@ -267,6 +267,22 @@ ppn_status ppn_select(ppn_scene* s, const double* g, double delta, const uint8_t
 ppn_status ppn_solve(ppn_scene* s, const double* x, const uint8_t* proj_mask, double* dx_out,
                      int32_t* ind_out, int32_t* iters_out);
 
+/* The projections and solves of one Newton iteration from the iterate x
+ * (Algorithm 1; for replaying a run iteration by iteration): the element
+ * Hessians are evaluated at x, then PN projects every element, PDN (with its
+ * countdown at 0) projects every element if the first solve reports
+ * indefiniteness and solves again, and PPN runs the inner loop from
+ * delta_in (INFINITY: not set yet, so the first round uses alpha |g|_inf).
+ * mask_out [n_tets] receives the elements projected by the end of the
+ * iteration, delta_out the delta carried to the next iteration (relaxed by
+ * beta; delta_in for PN and PDN) and ind_out the final solve's
+ * indefiniteness; any of them may be NULL.  x [3 n_verts]; the predictor
+ * comes from the scene state, which the call leaves unchanged, as it leaves
+ * the last step's statistics.  PPN_ERR_ARG for an unknown mode, a NULL x or
+ * delta_in not > 0; PPN_ERR_STATE for a non-finite gradient at x. */
+ppn_status ppn_debug_iterate(ppn_scene* s, int32_t mode, const double* x, double delta_in,
+                             uint8_t* mask_out, double* delta_out, int32_t* ind_out);
+
 /* Product q = H d [3 n_verts] with the assembled Hessian at x (Sec. 3; the
  * elements of proj_mask projected as in Eq. (5)). */
 ppn_status ppn_hessian_product(ppn_scene* s, const double* x, const uint8_t* proj_mask,

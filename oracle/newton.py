@@ -171,7 +171,7 @@ class Stepper:
         return de.sum() + di.sum() + dd.sum()
 
     # ---- one time step ----------------------------------------------------------
-    def step(self, mode: str, trace=False) -> StepStats:
+    def step(self, mode: str, trace=False, record_x=False) -> StepStats:
         if mode not in MODES:
             raise ValueError(mode)
         p, h = self.p, self.h
@@ -194,6 +194,8 @@ class Stepper:
                 g0 = g_l2
                 st.res0_l2 = g_l2
             rec = dict(k=k, g_l2=g_l2, g_inf=g_inf, delta_in=delta, rounds=[])
+            if record_x:
+                rec["x"] = x.copy()
             if p.stop_mode == "grad_rel" and g_l2 <= p.stop_tol * g0:
                 st.converged = True
                 if trace:
@@ -285,8 +287,9 @@ class Stepper:
         return st
 
 
-def run_scene(scene, mode, n_steps=None, params: Params = None, trace=False, callback=None):
-    """Run ``n_steps`` time steps of a ``scenes.Scene``; returns (stepper, [StepStats])."""
+def run_scene(scene, mode, n_steps=None, params: Params = None, trace=False, callback=None, record_x=False):
+    """Run ``n_steps`` time steps of a ``scenes.Scene``; returns (stepper, [StepStats]).
+    With ``trace`` and ``record_x`` each iteration record also holds its iterate x^k."""
     if params is None:
         params = Params(stop_mode=scene.stop_mode, stop_tol=scene.stop_tol)
     stp = Stepper(scene.X, scene.tets, scene.E, scene.nu, scene.rho, scene.dt, scene.gravity,
@@ -294,7 +297,7 @@ def run_scene(scene, mode, n_steps=None, params: Params = None, trace=False, cal
     out = []
     for n in range(1, (scene.n_steps if n_steps is None else n_steps) + 1):
         stp.set_targets(scene.targets(n))
-        out.append(stp.step(mode, trace=trace))
+        out.append(stp.step(mode, trace=trace, record_x=record_x))
         if callback is not None:
             callback(n, stp, out[-1])
     return stp, out

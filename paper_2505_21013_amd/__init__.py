@@ -258,6 +258,16 @@ class Scene:
         self._c(_abi.lib().ppn_select(self._h, _d(g), float(delta), _u8(m), _u8(out), C.byref(cnt)))
         return out, cnt.value
 
+    def ppn_debug_iterate(self, x, delta_in=float("inf"), mode="PPN"):
+        """(mask of projected elements, delta_out, ind) of one Newton iteration from x."""
+        x = _f64(x, 3 * self.N)
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        mask = np.empty(self.T, np.uint8)
+        dout, ind = C.c_double(), C.c_int32()
+        self._c(_abi.lib().ppn_debug_iterate(self._h, m, _d(x), float(delta_in), _u8(mask), C.byref(dout),
+                                            C.byref(ind)))
+        return mask, dout.value, bool(ind.value)
+
     def ppn_solve(self, x, proj_mask=None):
         x = _f64(x, 3 * self.N)
         dx = np.empty(3 * self.N)

@@ -100,6 +100,7 @@ SIGNATURES = {
     "ppn_eval_hessian": (C.c_int, [P, dp, u8p, ip, ip, dp]),
     "ppn_select": (C.c_int, [P, dp, C.c_double, u8p, u8p, ip]),
     "ppn_solve": (C.c_int, [P, dp, u8p, dp, ip, ip]),
+    "ppn_debug_iterate": (C.c_int, [P, C.c_int32, dp, C.c_double, u8p, dp, ip]),
     "ppn_hessian_product": (C.c_int, [P, dp, u8p, dp, dp]),
     "ppn_energy_difference": (C.c_int, [P, dp, dp, C.c_int32, dp, dp]),
     "ppn_project_batch_dev": (C.c_int, [P, P, C.c_int64, C.c_double, P]),

@@ -292,6 +292,15 @@ ppn_status ppn_solve(ppn_scene* s, const double* x, const uint8_t* proj_mask, do
   });
 }
 
+ppn_status ppn_debug_iterate(ppn_scene* s, int32_t mode, const double* x, double delta_in,
+                             uint8_t* mask_out, double* delta_out, int32_t* ind_out) {
+  IMPL(s);
+  return guarded(s, [&] {
+    S.debug_iterate(mode, x, delta_in, mask_out, delta_out, ind_out);
+    return PPN_OK;
+  });
+}
+
 ppn_status ppn_hessian_product(ppn_scene* s, const double* x, const uint8_t* proj_mask,
                                const double* d, double* q_out) {
   IMPL(s);

@@ -604,6 +604,59 @@ void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
 }
 
 // ---------------------------------------------------------------- one time step
+// The projections and solves of one Newton iteration at the evaluated iterate
+// (element Hessians assembled, nothing projected yet): PN projects every
+// element; PDN projects every element while its countdown runs and, when a
+// solve reports indefiniteness, projects every element, solves again and
+// restarts the countdown; PPN runs the inner loop of Algorithm 1 (delta
+// initialised to alpha |g|_inf, tightened by alpha after each indefinite
+// solve, relaxed by beta at the end).  Returns the final solve's
+// indefiniteness and updates delta and countdown.
+int32_t Scene::project_and_solve(int mode, double g_inf, double& delta, int& countdown,
+                                 ppn_step_stats& S, ppn_iter_record& rec) {
+  if (mode == PPN_PN || (mode == PPN_PDN && countdown > 0)) {
+    project_all();
+    if (mode == PPN_PDN) countdown--;
+  }
+  int32_t ind = 0, it = 0;
+  solve(ind, it);
+  S.solves++;
+  S.pcg_iters += it;
+  S.indefinite_solves += ind;
+  rec.first_ind = ind;
+  rec.first_iters = it;
+  if (mode == PPN_PDN && ind && !all_projected_) {
+    project_all();
+    solve(ind, it);
+    S.solves++;
+    S.pcg_iters += it;
+    S.indefinite_solves += ind;
+    countdown = prm_.pdn_countdown;
+  }
+  if (mode == PPN_PPN) {
+    while (ind) {
+      if (std::isinf(delta)) delta = prm_.alpha * g_inf;
+      const int32_t n_new = select_and_project(delta, delta <= prm_.eps_delta);
+      S.inner_rounds++;
+      rec.rounds++;
+      if (n_new > 0) {
+        solve(ind, it);
+        S.solves++;
+        S.pcg_iters += it;
+        S.indefinite_solves += ind;
+      } else {
+        // Nothing new was projected: H is unchanged and the solve would
+        // repeat the previous one exactly (still indefinite).
+        S.skipped_solves++;
+      }
+      if (ind) delta = prm_.alpha * delta;
+      if (ind && all_projected_) break;
+    }
+    delta = prm_.beta * delta;
+  }
+  return ind;
+}
+
 ppn_status Scene::newton_step(int mode, ppn_step_stats* out) {
   if (!loaded()) fail("no mesh loaded");
   if (mode != PPN_PN && mode != PPN_PDN && mode != PPN_PPN) fail("unknown mode");
@@ -649,46 +702,7 @@ ppn_status Scene::newton_step(int mode, ppn_step_stats* out) {
       }
       break;
     }
-    if (mode == PPN_PN || (mode == PPN_PDN && countdown > 0)) {
-      project_all();
-      if (mode == PPN_PDN) countdown--;
-    }
-    int32_t ind = 0, it = 0;
-    solve(ind, it);
-    S.solves++;
-    S.pcg_iters += it;
-    S.indefinite_solves += ind;
-    rec.first_ind = ind;
-    rec.first_iters = it;
-    if (mode == PPN_PDN && ind && !all_projected_) {
-      project_all();
-      solve(ind, it);
-      S.solves++;
-      S.pcg_iters += it;
-      S.indefinite_solves += ind;
-      countdown = prm_.pdn_countdown;
-    }
-    if (mode == PPN_PPN) {
-      while (ind) {
-        if (std::isinf(delta)) delta = prm_.alpha * g_inf;
-        const int32_t n_new = select_and_project(delta, delta <= prm_.eps_delta);
-        S.inner_rounds++;
-        rec.rounds++;
-        if (n_new > 0) {
-          solve(ind, it);
-          S.solves++;
-          S.pcg_iters += it;
-          S.indefinite_solves += ind;
-        } else {
-          // Nothing new was projected: H is unchanged and the solve would
-          // repeat the previous one exactly (still indefinite).
-          S.skipped_solves++;
-        }
-        if (ind) delta = prm_.alpha * delta;
-        if (ind && all_projected_) break;
-      }
-      delta = prm_.beta * delta;
-    }
+    const int32_t ind = project_and_solve(mode, g_inf, delta, countdown, S, rec);
     rec.last_ind = ind;
     rec.delta_out = delta;
     rec.n_projected = n_projected_;
@@ -862,6 +876,29 @@ void Scene::solve_at(const double* x, const uint8_t* mask, double* dx, int32_t* 
   sync();
   if (ind) *ind = i1;
   if (iters) *iters = i2;
+}
+
+void Scene::debug_iterate(int mode, const double* x, double delta_in, uint8_t* mask_out,
+                          double* delta_out, int32_t* ind_out) {
+  if (mode != PPN_PN && mode != PPN_PDN && mode != PPN_PPN) fail("unknown mode");
+  if (!(delta_in > 0.0)) fail("delta_in must be > 0 (INFINITY: not set yet)");
+  stage_state(x);
+  RestoreX r{this, D_, st_};
+  const ppn_step_stats saved = last_stats;
+  evaluate_at_current_x();
+  read_scal(2, hscal_);
+  const double g_inf = hscal_[1];
+  if (!std::isfinite(g_inf)) fail("non-finite gradient", PPN_ERR_STATE);
+  double delta = delta_in;
+  int countdown = 0;
+  ppn_step_stats S{};
+  ppn_iter_record rec{};
+  const int32_t ind = project_and_solve(mode, g_inf, delta, countdown, S, rec);
+  last_stats = saved;
+  if (mask_out) HIPCHK(hipMemcpyAsync(mask_out, D_.proj, size_t(D_.T), hipMemcpyDeviceToHost, st_));
+  sync();
+  if (delta_out) *delta_out = delta;
+  if (ind_out) *ind_out = ind;
 }
 
 void Scene::hessian_product(const double* x, const uint8_t* mask, const double* d, double* q) {

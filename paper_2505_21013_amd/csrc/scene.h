@@ -48,6 +48,8 @@ class Scene {
                     double* vals);
   void select(const double* g, double delta, const uint8_t* proj_in, uint8_t* mask, int32_t* cnt);
   void solve_at(const double* x, const uint8_t* mask, double* dx, int32_t* ind, int32_t* iters);
+  void debug_iterate(int mode, const double* x, double delta_in, uint8_t* mask_out, double* delta_out,
+                     int32_t* ind_out);
   void hessian_product(const double* x, const uint8_t* mask, const double* d, double* q);
   void energy_difference(const double* x, const double* dx, int32_t n, const double* gam,
                          double* out);
@@ -81,6 +83,8 @@ class Scene {
   void project_mask(const uint8_t* mask);
   void project_all();
   int32_t select_and_project(double delta, bool fallback);
+  int32_t project_and_solve(int mode, double g_inf, double& delta, int& countdown, ppn_step_stats& S,
+                            ppn_iter_record& rec);
   void solve(int32_t& ind, int32_t& iters);
   // One PCG run of the given arithmetic on the system whose right-hand side is
   // sign * src; returns its indefiniteness flag and iteration count.
