@@ -35,6 +35,28 @@ __device__ inline double block_sum(double v, double* lds) {
   return s;
 }
 
+// Sums of two values over the workgroup, each in block_sum's order (so with
+// the same bits), for one barrier round instead of two; lds: 16 doubles (up
+// to 8 wavefronts).
+__device__ inline void block_sum2(double& a, double& b, double* lds) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    lds[w] = a;
+    lds[8 + w] = b;
+  }
+  __syncthreads();
+  double sa = lds[0], sb = lds[8];
+  for (int k = 1; k < nw; ++k) {
+    sa += lds[k];
+    sb += lds[8 + k];
+  }
+  a = sa;
+  b = sb;
+}
+
 __device__ inline double block_max(double v, double* lds) {
   v = wave_max(v);
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;

@@ -363,8 +363,7 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
       rr += r[c] * r[c];
     }
   }
-  rr = block_sum(rr, lds);  // synchronises: sx and sr are complete
-  rzn = block_sum(rzn, lds);
+  block_sum2(rr, rzn, lds);  // synchronises: sx and sr are complete
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int64_t f = f0 + k * kPcgBlock + t;
