@@ -80,8 +80,8 @@ def cpu_baseline(cfg, per_step_counts):
 def run_form(a, precision, torch, np):
     """Warm-up steps, reset to the initial state, then K timed steps."""
     from paper_2505_21013_amd import PPN_FP64, PPN_MIXED, scene_from
-    from scenes import config
-    sc = config(a.config)
+    from scenes import config, cube_compress
+    sc = cube_compress(n=a.cells) if a.cells and a.config == 2 else config(a.config)
     stream = torch.cuda.current_stream().cuda_stream
     s = scene_from(sc, stream=stream, precision=PPN_MIXED if precision == "mixed" else PPN_FP64)
     info = s.ppn_scene_info()
@@ -356,6 +356,9 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64 or mixed alone, or both (FP64 headline, mixed reported beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cells", type=int, default=None,
+                    help="compressed cube of N^3 cells instead of 64^3 (size studies: no CPU baseline, and no "
+                         "counter traffic, which was measured at 64^3)")
     ap.add_argument("--stats-out", default=None, help="write per-step stats JSON here")
     ap.add_argument("--batch", action="store_true",
                     help="batched workload instead: 64 independent scenes through the serving engine")
@@ -421,7 +424,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if headline == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": (f"cube 64^3 cells -> {info['n_tets']} tets / {info['n_verts']} verts, "
+        "config": {"workload": (f"cube {a.cells or 64}^3 cells -> {info['n_tets']} tets / {info['n_verts']} verts, "
                                 f"SNH E log-uniform [1e4,1e6] Pa, nu 0.48, dt 1/30 s, top pushed down "
                                 f"60% over 50 steps; steps 1..{K}; mode {a.mode}"
                                 if a.config == 2 else f"configuration {a.config}, mode {a.mode}"),
@@ -430,7 +433,8 @@ def main():
                    "parallelism": "single GPU"},
     }
     out.update(summary(R, K, info, np))
-    out["roofline"] = roofline(R, headline, info, a.config)
+    cfg = a.config if not a.cells else None
+    out["roofline"] = roofline(R, headline, info, cfg)
     out["composite_roofline"] = composite_roofline(R, headline, info, K)
     if "mixed" in runs and headline == "fp64":
         M = runs["mixed"]
@@ -441,13 +445,13 @@ def main():
         m.update(summary(M, K, info, np))
         m["refine_rounds_per_solve"] = M["tot"]["refine_rounds"] / max(M["tot"]["solves"], 1)
         m["max_position_diff_vs_fp64_run"] = float(np.max(np.abs(M["x"] - R["x"]))) / diag
-        m["roofline"] = roofline(M, "mixed", info, a.config)
+        m["roofline"] = roofline(M, "mixed", info, cfg)
         m["composite_roofline"] = composite_roofline(M, "mixed", info, K)
         out["mixed"] = m
     if a.stats_out:
         with open(a.stats_out, "w") as f:
             json.dump(stats, f)
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and not a.cells:
         tot = R["tot"]
         counts = {"newton_iters": tot["newton_iters"] / K, "pcg_iters": tot["pcg_iters"] / K,
                   "projected": tot["projected"] / K,
