@@ -74,3 +74,13 @@ def test_renumbered_is_the_same_mesh():
         got = dict(zip(old[r.dirichlet_ids].tolist(), map(tuple, r.targets(n))))
         want = dict(zip(s.dirichlet_ids.tolist(), map(tuple, s.targets(n))))
         assert got == want
+
+
+def test_renumbering_twice_composes_the_maps():
+    """A renumbered copy of a renumbered scene keeps maps to the original ids."""
+    from scenes import cube_compress, renumbered
+    s = cube_compress(n=3, n_steps=2, ramp_steps=2)
+    r2 = renumbered(renumbered(s, seed=1), seed=2)
+    old, tmap = r2.meta["vertex_of_new"], r2.meta["tet_of_new"]
+    assert np.array_equal(r2.X, s.X[old]) and np.array_equal(r2.E, s.E[tmap])
+    assert np.array_equal(np.sort(old[r2.tets], axis=1), np.sort(s.tets[tmap], axis=1))
