@@ -32,7 +32,7 @@ from oracle.fem import predictor
 from oracle.pcg import pcg_block_jacobi
 from oracle.project import project_to_pd
 from paper_2505_21013_amd import PPN_MIXED, run_steps
-from scenes import config, cube_compress
+from scenes import config, cube_compress, renumbered
 
 from helpers import gpu_scene, oracle_stepper, squashed_state
 
@@ -108,7 +108,18 @@ def _mask_mismatch(o_trace, g_trace):
 
 @pytest.mark.parametrize("mode", ["PN", "PDN", "PPN"])
 def test_mixed_cube6_jitter_20_steps(mode):
-    sc = config(0)
+    _mixed_against_oracle(config(0), mode)
+
+
+@pytest.mark.parametrize("mode", ["PN", "PPN"])
+def test_mixed_renumbered_cube6_jitter_20_steps(mode):
+    """The same scene numbered at random (vertices, elements, local orders):
+    the FP32 matrix conversion and product then work on 64-row groups of
+    mixed row lengths with scattered columns, and must meet the same bars."""
+    _mixed_against_oracle(renumbered(config(0), seed=5), mode)
+
+
+def _mixed_against_oracle(sc, mode):
     orc_x = []
     _, ost = oracle.run_scene(sc, mode, n_steps=sc.n_steps, trace=True,
                               callback=lambda n, s, st: orc_x.append(s.x.copy()))
