@@ -295,8 +295,14 @@ ppn_status ppn_energy_difference(ppn_scene* s, const double* x, const double* dx
 
 /* Stateless batched projection (Sec. 3, Eq. (4)) of n symmetric 12x12 row-major
  * matrices in device memory: Hhat = H + sum_{lambda_i < eps} (eps - lambda_i) q_i q_i^T.
- * In and out may alias.  Runs on hip_stream (NULL = default stream) and
- * returns after the kernel finished. */
+ * Precondition: every matrix is a linear-tetrahedron element Hessian, i.e.
+ * symmetric and annihilating the three rigid translations (b_0 + b_1 + b_2 +
+ * b_3 = 0, so in each row the four vertex columns of a coordinate sum to zero);
+ * the solver deflates those exactly and clamps their zero eigenvalues to eps.
+ * Both are checked first, to 1e-9 of each matrix's largest entry: a violation
+ * (or a NaN) returns PPN_ERR_ARG with nothing written.  In and out may alias.
+ * Runs on hip_stream (NULL = default stream) and returns after the kernels
+ * finished; concurrent calls are serialised. */
 ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t n, double eps,
                                  void* hip_stream);
 
@@ -390,7 +396,9 @@ ppn_status ppn_engine_submit(ppn_engine* e, int32_t scene_id, int32_t mode, cons
  * status (PPN_OK, a warning, or the error that ended it, with the message in
  * ppn_last_error(NULL) of the calling thread); stats_out its statistics;
  * latency_ms_out the time from submission to completion and queue_ms_out the
- * time it waited before a worker took it.  Any output may be NULL. */
+ * time it waited before a worker took it.  Any output may be NULL.  The
+ * request's record is freed when its wait returns: a later wait on the same id
+ * returns PPN_ERR_ARG (ids are never reused). */
 ppn_status ppn_engine_wait(ppn_engine* e, int64_t request_id, ppn_status* step_status_out,
                            ppn_step_stats* stats_out, double* latency_ms_out, double* queue_ms_out);
 /* Positions and velocities [n_verts][3] of a scene once all its submitted

@@ -159,6 +159,12 @@ class Stepper:
         gv = np.abs(g.reshape(-1, 3)).max(axis=1)
         return gv[self.mesh.tets].max(axis=1)
 
+    def select(self, g, delta, projected):
+        """Elements projected by one round of Algorithm 1's inner loop (Sec. 4):
+        not projected yet in this Newton iteration, and |S^e g|_inf > delta
+        (strict), or every such element once delta <= eps_delta."""
+        return ~projected & ((self.selection_residual(g) > delta) | (delta <= self.p.eps_delta))
+
     def energy_difference(self, x, dx, gamma, psi_x=None):
         """Psi(x + gamma dx) - Psi(x), summed per term."""
         if psi_x is None:
@@ -169,6 +175,22 @@ class Stepper:
         sd = step[self.dir_ids]
         dd = 0.5 * self.p.k_dirichlet * np.sum(sd * (2.0 * (x[self.dir_ids] - self.xbar) + sd), axis=1)
         return de.sum() + di.sum() + dd.sum()
+
+    def line_search(self, x, dx, g):
+        """Backtracking line search for sufficient descent (Sec. 5.1): try
+        gamma = 1, 1/2, 1/4, ... and accept the first with
+        Psi(x + gamma dx) - Psi(x) <= c gamma g.dx, after at most ls_maxit
+        halvings.  Returns (gamma, accepted, rejected trials); after a failure
+        every one of the ls_maxit + 1 trials was rejected."""
+        p = self.p
+        gdx = float(g @ dx.reshape(-1))
+        psi_x = element_psi(self.mesh, x)
+        gamma = 1.0
+        for rejected in range(p.ls_maxit + 1):
+            if self.energy_difference(x, dx, gamma, psi_x) <= p.armijo_c * gamma * gdx:
+                return gamma, True, rejected
+            gamma *= 0.5
+        return gamma, False, p.ls_maxit + 1
 
     # ---- one time step ----------------------------------------------------------
     def step(self, mode: str, trace=False, record_x=False) -> StepStats:
@@ -226,6 +248,7 @@ class Stepper:
                 project(np.nonzero(~projected)[0])
                 if mode == "PDN":
                     countdown -= 1
+            rec["pre_projected"] = int(projected.sum())
             dx, ind, it = solve()
             rec["first"] = (bool(ind), it)
             if mode == "PDN" and ind and not projected.all():
@@ -236,8 +259,7 @@ class Stepper:
                 while ind:
                     if delta == math.inf:
                         delta = p.alpha * g_inf
-                    s = self.selection_residual(g)
-                    sel = np.nonzero(~projected & ((s > delta) | (delta <= p.eps_delta)))[0]
+                    sel = np.nonzero(self.select(g, delta, projected))[0]
                     project(sel)
                     st.inner_rounds += 1
                     dx, ind, it = solve()
@@ -264,16 +286,8 @@ class Stepper:
                     st.trace.append(rec)
                 break
 
-            gdx = float(g @ dx)
-            psi_x = element_psi(self.mesh, x)
-            gamma = 1.0
-            accepted = False
-            for ls in range(p.ls_maxit + 1):
-                if self.energy_difference(x, dxv, gamma, psi_x) <= p.armijo_c * gamma * gdx:
-                    accepted = True
-                    break
-                gamma *= 0.5
-                st.ls_backtracks += 1
+            gamma, accepted, rejected = self.line_search(x, dxv, g)
+            st.ls_backtracks += rejected
             rec["gamma"] = gamma if accepted else 0.0
             if trace:
                 st.trace.append(rec)

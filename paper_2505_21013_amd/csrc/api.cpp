@@ -1,6 +1,7 @@
 // extern "C" boundary of libppn: argument checks, exception capture, status codes.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -20,6 +21,10 @@ struct ppn_engine {
 namespace {
 
 thread_local std::string g_error;
+
+// Relative tolerance of the dense projector's precondition (symmetry and the
+// translation null space), far above the rounding of FP64 element Hessians.
+constexpr double kDenseCheckRtol = 1e-9;
 
 template <class F>
 ppn_status guarded(ppn_scene* s, F&& f) {
@@ -326,8 +331,29 @@ ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t 
     return PPN_ERR_ARG;
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  ppn::launch_project_batch(H_dev, Hhat_dev, n, eps, st);
-  hipError_t e = hipGetLastError();
+  // The precondition is checked before anything is written (the output may
+  // alias the input).  The flag lives in pinned host memory that the check
+  // kernel writes; calls are serialised around it.
+  static std::mutex mu;
+  static int32_t* bad = nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  hipError_t e = hipSuccess;
+  if (!bad) e = hipHostMalloc(reinterpret_cast<void**>(&bad), 64, hipHostMallocDefault);
+  if (e == hipSuccess) {
+    *bad = 0;
+    ppn::launch_check_dense(H_dev, n, kDenseCheckRtol, bad, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && *bad) {
+    g_error = "ppn_project_batch_dev: an input matrix is not symmetric or does not annihilate the "
+              "rigid translations (tolerance 1e-9 of its largest entry); nothing was written";
+    return PPN_ERR_ARG;
+  }
+  if (e == hipSuccess) {
+    ppn::launch_project_batch(H_dev, Hhat_dev, n, eps, st);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     g_error = std::string("ppn_project_batch_dev: ") + hipGetErrorString(e);

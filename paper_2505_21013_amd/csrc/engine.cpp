@@ -108,8 +108,8 @@ int64_t Engine::submit(int32_t scene, int32_t mode, const double* targets) {
   r->targets.assign(targets, targets + nt);
   r->t_submit = Clock::now();
   pending_.push_back(r.get());
-  requests_.push_back(std::move(r));
-  const int64_t id = requests_.back()->id;
+  const int64_t id = r->id;
+  requests_.emplace(id, std::move(r));
   lk.unlock();
   cv_work_.notify_one();
   return id;
@@ -243,14 +243,18 @@ void Engine::worker() {
 ppn_status Engine::wait(int64_t id, ppn_step_stats* stats, double* latency_ms, double* queue_ms,
                         std::string* error) {
   std::unique_lock<std::mutex> lk(mu_);
-  if (id < 1 || id > int64_t(requests_.size())) fail_arg("unknown request id");
-  Request& r = *requests_[size_t(id - 1)];
+  auto it = requests_.find(id);
+  if (it == requests_.end()) fail_arg("unknown request id (or already waited on)");
+  Request& r = *it->second;
+  ++r.waiters;
   cv_done_.wait(lk, [&] { return r.done; });
   if (stats) *stats = r.stats;
   if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
   if (queue_ms) *queue_ms = std::chrono::duration<double, std::milli>(r.t_start - r.t_submit).count();
   if (error) *error = r.error;
-  return r.status;
+  const ppn_status st = r.status;
+  if (--r.waiters == 0) requests_.erase(id);  // the record is freed once waited on
+  return st;
 }
 
 void Engine::get_state(int32_t scene, double* x, double* v) {

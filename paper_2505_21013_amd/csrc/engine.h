@@ -20,6 +20,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ppn.h"
@@ -75,6 +76,7 @@ class Engine {
     ppn_status status = PPN_OK;
     ppn_step_stats stats{};
     std::string error;
+    int waiters = 0;  // threads inside wait() for this request
   };
 
   void worker();
@@ -95,7 +97,8 @@ class Engine {
   std::condition_variable cv_work_, cv_done_;
   std::vector<std::unique_ptr<Slot>> slots_;
   std::deque<Request*> pending_;
-  std::vector<std::unique_ptr<Request>> requests_;  // by id - 1
+  // Requests not waited on yet; a record is freed when a wait on it returns.
+  std::unordered_map<int64_t, std::unique_ptr<Request>> requests_;
   std::vector<std::thread> workers_;
 };
 

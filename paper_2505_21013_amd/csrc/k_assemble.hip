@@ -202,6 +202,7 @@ __device__ inline bool selected(const Dev& D, int e, double delta, int fallback)
 }
 
 __global__ __launch_bounds__(kBlock) void k_select_count(Dev D, double delta, int fallback) {
+  static_assert(kBlock == 4 * 64, "k_select_count adds the counts of exactly four wavefronts");
   __shared__ int cnt[kBlock / 64];
   const int e = blockIdx.x * kBlock + threadIdx.x;
   const bool p = (e < D.T) && selected(D, e, delta, fallback);

@@ -365,6 +365,30 @@ __global__ __launch_bounds__(kBlock) void k_eig_dense(const double* in, double* 
   project_one<T>(Guarded<DenseIO>{io, live}, eps, false);
 }
 
+// Precondition of the dense projector, which deflates the translations
+// exactly: each matrix is symmetric and annihilates the three rigid
+// translations (in every row, the four vertex columns of each coordinate sum
+// to zero), both up to rtol times its largest entry.  A matrix that fails (or
+// holds a NaN) sets *bad = 1; every writer stores the same value.
+__global__ __launch_bounds__(kBlock) void k_check_dense(const double* in, int64_t n, double rtol,
+                                                        int32_t* bad) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const double* H = in + 144 * k;
+  double amax = 0.0, trans = 0.0, asym = 0.0;
+  for (int r = 0; r < 12; ++r) {
+    for (int c = 0; c < 3; ++c) {
+      const double t = ((H[12 * r + c] + H[12 * r + 3 + c]) + H[12 * r + 6 + c]) + H[12 * r + 9 + c];
+      trans = fmax(trans, fabs(t));
+    }
+    for (int c = 0; c < 12; ++c) {
+      amax = fmax(amax, fabs(H[12 * r + c]));
+      if (c > r) asym = fmax(asym, fabs(H[12 * r + c] - H[12 * c + r]));
+    }
+  }
+  if (!(trans <= rtol * amax) || !(asym <= rtol * amax)) *bad = 1;
+}
+
 // Full 12x12 element matrices gathered from the slots (debug / parity output).
 __global__ __launch_bounds__(kBlock) void k_elem_dense(Dev D, const int32_t* ids, int n,
                                                         double* out) {
@@ -402,6 +426,11 @@ void launch_eig_list_f32(const Dev& D, int32_t n, double eps, int mirror, hipStr
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st) {
   if (n <= 0) return;
   k_eig_dense<double><<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(H, out, n, eps);
+}
+
+void launch_check_dense(const double* H, int64_t n, double rtol, int32_t* bad, hipStream_t st) {
+  if (n <= 0) return;
+  k_check_dense<<<unsigned((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(H, n, rtol, bad);
 }
 
 void launch_element_hessians(const Dev& D, const int32_t* ids, int32_t n, double* out,

@@ -56,6 +56,18 @@ __device__ inline void pcg_finish(const Dev& D, int w, int ind, int iters) {
   }
 }
 
+// Whether the solve has ended.  Workgroup 0 of a launch may record the end
+// while other workgroups of the same launch start, so the flag is read once per
+// workgroup and shared through LDS: all waves of a workgroup take the same
+// branch (a wave that returned alone would leave the others summing stale LDS
+// partials after the next barrier).
+__device__ __forceinline__ bool solve_done(const PcgState* pcg) {
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = *reinterpret_cast<const volatile int32_t*>(&pcg->done);
+  __syncthreads();
+  return s_done != 0;
+}
+
 // r = sign * src, x = 0, z = P^-1 r into zd[0]; partials of r^T r, r^T z and
 // the count of diagonal blocks failing Sylvester's criterion.
 // The bodies below take the scene's logical workgroup index w (0 .. Gp-1):
@@ -222,7 +234,7 @@ template <typename M, bool kFirst, int kLoad>
 __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, int j, double tol2,
                                               int maxit, int w) {
   __shared__ double lds[16];
-  if (D.pcg->done) return;
+  if (solve_done(D.pcg)) return;
   const int Gp = D.Gp;
   const double* zcur = V.zd + ((j & 1) ? 6 * size_t(D.N) : 0);
   double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(D.N));
@@ -242,6 +254,8 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   sa = wave_sum(sa);
   sb = wave_sum(sb);
   if (kFirst) sc = wave_sum(sc);
+  // The combination below is written out for the four wavefronts of a workgroup.
+  static_assert(kPcgBlock == 4 * 64, "pcg_spmv_body sums the partials of exactly four wavefronts");
   const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     lds[wv] = sa;
@@ -319,7 +333,7 @@ template <typename M, bool kStream>
 __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V, int j, int w) {
   __shared__ double lds[16];
   __shared__ double sq[3 * kPcgBlock], sr[3 * kPcgBlock], sx[3 * kPcgBlock];
-  if (D.pcg->done) return;
+  if (solve_done(D.pcg)) return;
   const int Gp = D.Gp, N = D.N;
   double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(N));
   const int t = threadIdx.x;

@@ -147,6 +147,24 @@ def test_engine_admission_by_footprint():
         assert np.array_equal(st_want[i][0], st_got[i][0])
 
 
+def test_engine_request_record_is_freed_after_its_wait():
+    """A request is waited on once: its record is freed then, so a second wait on
+    the same id is an argument error, while other requests are unaffected."""
+    from paper_2505_21013_amd import PPNError
+    sc = _small_scenes(1)[0]
+    with Engine(n_workers=1) as e:
+        sid = e.add_scene(sc)
+        r1 = e.ppn_engine_submit(sid, "PPN", sc.targets(1))
+        r2 = e.ppn_engine_submit(sid, "PPN", sc.targets(2))
+        assert e.ppn_engine_wait(r1)["status"] == "PPN_OK"
+        with pytest.raises(PPNError) as ei:
+            e.ppn_engine_wait(r1)
+        assert ei.value.code == -1
+        assert e.ppn_engine_wait(r2)["status"] == "PPN_OK"
+        with pytest.raises(PPNError):
+            e.ppn_engine_wait(r2 + 1000)
+
+
 def test_engine_oversized_scene_is_refused():
     sc = _small_scenes(1)[0]
     with Engine(n_workers=1, mem_budget_bytes=1 << 20) as e:

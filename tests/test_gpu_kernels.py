@@ -183,3 +183,37 @@ def test_project_batch_known_spectra():
     # in place (aliased input and output)
     ppn_project_batch_dev(dev, dev, n, 1e-8)
     assert np.array_equal(dev.cpu().numpy().reshape(n, 12, 12), got)
+
+
+def test_project_batch_rejects_matrices_outside_its_precondition():
+    """The dense projector deflates the rigid translations exactly, so it takes
+    only symmetric matrices that annihilate them: -I, an asymmetric element
+    Hessian and a NaN entry are each refused with PPN_ERR_ARG, and nothing is
+    written (the output keeps its sentinel values)."""
+    torch = pytest.importorskip("torch")
+    from paper_2505_21013_amd import PPNError, ppn_project_batch_dev
+    had = 0.5 * np.array([[1, 1, 1, 1], [1, 1, -1, -1], [1, -1, 1, -1], [1, -1, -1, 1]], float)
+    U = np.kron(had, np.eye(3))
+    Z = np.zeros((12, 12))
+    Z[3:, 3:] = np.diag(np.arange(-4.0, 5.0))
+    good = U @ Z @ U
+    good = 0.5 * (good + good.T)
+    asym = good.copy()
+    asym[3, 7] += 1e-3 * np.abs(good).max()
+    nan = good.copy()
+    nan[5, 5] = np.nan
+    for bad in (-np.eye(12), asym, nan):
+        Hs = np.stack([good, bad, good])
+        dev = torch.from_numpy(Hs.reshape(-1)).cuda()
+        out = torch.full_like(dev, 7.0)
+        with pytest.raises(PPNError) as ei:
+            ppn_project_batch_dev(dev, out, 3, 1e-8)
+        assert ei.value.code == -1
+        assert torch.all(out == 7.0).item()
+        # aliased: the input is left untouched too
+        with pytest.raises(PPNError):
+            ppn_project_batch_dev(dev, dev, 3, 1e-8)
+        assert np.array_equal(dev.cpu().numpy(), Hs.reshape(-1), equal_nan=True)
+    ok = torch.from_numpy(np.stack([good] * 3).reshape(-1)).cuda()
+    ppn_project_batch_dev(ok, ok, 3, 1e-8)
+    assert np.linalg.eigvalsh(ok.cpu().numpy().reshape(3, 12, 12)[0]).min() >= 1e-8 - 1e-12
