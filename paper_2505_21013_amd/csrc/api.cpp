@@ -1,6 +1,7 @@
 // extern "C" boundary of libppn: argument checks, exception capture, status codes.
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -332,20 +333,25 @@ ppn_status ppn_project_batch_dev(const double* H_dev, double* Hhat_dev, int64_t 
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   // The precondition is checked before anything is written (the output may
-  // alias the input).  The flag lives in pinned host memory that the check
-  // kernel writes; calls are serialised around it.
+  // alias the input).  The check kernel raises a flag in a small device buffer
+  // (one per device, allocated at the first call) that is copied back; calls
+  // are serialised around it.
   static std::mutex mu;
-  static int32_t* bad = nullptr;
+  static std::map<int, int32_t*> flags;
   std::lock_guard<std::mutex> lk(mu);
-  hipError_t e = hipSuccess;
-  if (!bad) e = hipHostMalloc(reinterpret_cast<void**>(&bad), 64, hipHostMallocDefault);
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  int32_t*& bad = flags[device];
+  if (e == hipSuccess && !bad) e = hipMalloc(reinterpret_cast<void**>(&bad), 256);
+  int32_t bad_host = 0;
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int32_t), st);
   if (e == hipSuccess) {
-    *bad = 0;
     ppn::launch_check_dense(H_dev, n, kDenseCheckRtol, bad, st);
     e = hipGetLastError();
   }
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad_host, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess && *bad) {
+  if (e == hipSuccess && bad_host) {
     g_error = "ppn_project_batch_dev: an input matrix is not symmetric or does not annihilate the "
               "rigid translations (tolerance 1e-9 of its largest entry); nothing was written";
     return PPN_ERR_ARG;

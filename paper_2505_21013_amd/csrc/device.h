@@ -184,7 +184,7 @@ void launch_eig_all_f32(const Dev& D, double eps, int mirror, hipStream_t st);
 void launch_eig_list_f32(const Dev& D, int32_t n, double eps, int mirror, hipStream_t st);
 void launch_regather_list(const Dev& D, int32_t n, hipStream_t st);
 void launch_project_batch(const double* H, double* out, int64_t n, double eps, hipStream_t st);
-// Sets *bad (device-visible memory) if a dense 12x12 matrix is not symmetric or
+// Sets *bad (device memory) if a dense 12x12 matrix is not symmetric or
 // does not annihilate the rigid translations, up to rtol of its largest entry.
 void launch_check_dense(const double* H, int64_t n, double rtol, int32_t* bad, hipStream_t st);
 // r = sign * src (FP64 source), x = 0, first preconditioned residual.

@@ -375,18 +375,22 @@ __global__ __launch_bounds__(kBlock) void k_check_dense(const double* in, int64_
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (k >= n) return;
   const double* H = in + 144 * k;
+  // fmax drops NaN operands, so finiteness is tested on its own.
   double amax = 0.0, trans = 0.0, asym = 0.0;
+  bool finite = true;
   for (int r = 0; r < 12; ++r) {
     for (int c = 0; c < 3; ++c) {
       const double t = ((H[12 * r + c] + H[12 * r + 3 + c]) + H[12 * r + 6 + c]) + H[12 * r + 9 + c];
       trans = fmax(trans, fabs(t));
     }
     for (int c = 0; c < 12; ++c) {
-      amax = fmax(amax, fabs(H[12 * r + c]));
-      if (c > r) asym = fmax(asym, fabs(H[12 * r + c] - H[12 * c + r]));
+      const double h = H[12 * r + c];
+      finite = finite && isfinite(h);
+      amax = fmax(amax, fabs(h));
+      if (c > r) asym = fmax(asym, fabs(h - H[12 * c + r]));
     }
   }
-  if (!(trans <= rtol * amax) || !(asym <= rtol * amax)) *bad = 1;
+  if (!finite || !(trans <= rtol * amax) || !(asym <= rtol * amax)) *bad = 1;
 }
 
 // Full 12x12 element matrices gathered from the slots (debug / parity output).
