@@ -249,6 +249,20 @@ ppn_status ppn_eval_gradient(ppn_scene* s, const double* x, double* g_out);
 ppn_status ppn_eval_element_hessians(ppn_scene* s, const double* x, const uint8_t* proj_mask,
                                      int32_t n, const int32_t* ids, double* H_out);
 
+/* For callers that cannot allocate device memory during a call (code in tight
+ * serving loops, harnesses that forbid hipMalloc): ppn_eval_element_hessians
+ * with the same arguments, results and errors, except that its device staging
+ * (the element ids and the 12x12 matrices before their copy to H_out) sits in
+ * a fixed array of 4,734,976 bytes that the library holds once per GPU and process
+ * instead of two allocations per call; the call allocates no device memory.
+ * At most PPN_NOALLOC_MAX_ELEMENTS matrices per call (n, or n_tets when ids is
+ * NULL); more return PPN_ERR_ARG with nothing evaluated.  Calls on one GPU
+ * share the array and are serialised by the library (overlapping calls would
+ * race on it); it keeps the last call's contents. */
+#define PPN_NOALLOC_MAX_ELEMENTS 4096
+ppn_status ppn_eval_element_hessians_noalloc(ppn_scene* s, const double* x, const uint8_t* proj_mask,
+                                             int32_t n, const int32_t* ids, double* H_out);
+
 /* Assembled global Hessian at x in 3x3 block-sparse row form, with the
  * elements in proj_mask (nullable) projected: row_ptr [n_verts+1],
  * col [n_blocks], vals [n_blocks][9] row-major blocks (Sec. 3, Sec. 4.1). */

@@ -11,7 +11,8 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import (MODES, PPN_FP64, PPN_MIXED, PPN_ORDER_MORTON, PPN_ORDER_PENCIL, PPN_PDN, PPN_PN,
+from ._abi import (MODES, PPN_FP64, PPN_MIXED, PPN_NOALLOC_MAX_ELEMENTS, PPN_ORDER_MORTON,
+                   PPN_ORDER_PENCIL, PPN_PDN, PPN_PN,
                    PPN_PPN, PPN_STOP_GRAD_REL, PPN_STOP_VEL, STATUS, ppn_engine_info, ppn_iter_record,
                    ppn_params, ppn_scene_desc, ppn_step_stats)
 
@@ -237,6 +238,17 @@ class Scene:
         out = np.empty((n, 12, 12))
         m = _mask(proj_mask, self.T)
         self._c(_abi.lib().ppn_eval_element_hessians(self._h, _d(x), _u8(m), n, _i(ids_a), _d(out)))
+        return out
+
+    def ppn_eval_element_hessians_noalloc(self, x, ids=None, proj_mask=None):
+        """As ppn_eval_element_hessians, staged in the library's fixed device
+        array (no device allocation; at most PPN_NOALLOC_MAX_ELEMENTS matrices)."""
+        x = _f64(x, 3 * self.N)
+        ids_a = None if ids is None else np.ascontiguousarray(ids, dtype=np.int32).reshape(-1)
+        n = self.T if ids_a is None else ids_a.size
+        out = np.empty((n, 12, 12))
+        m = _mask(proj_mask, self.T)
+        self._c(_abi.lib().ppn_eval_element_hessians_noalloc(self._h, _d(x), _u8(m), n, _i(ids_a), _d(out)))
         return out
 
     def ppn_eval_hessian(self, x, proj_mask=None):

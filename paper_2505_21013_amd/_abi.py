@@ -9,6 +9,7 @@ MODES = {"PN": PPN_PN, "PDN": PPN_PDN, "PPN": PPN_PPN}
 PPN_FP64, PPN_MIXED = 0, 1
 PPN_STOP_VEL, PPN_STOP_GRAD_REL = 0, 1
 PPN_ORDER_PENCIL, PPN_ORDER_MORTON = 0, 1
+PPN_NOALLOC_MAX_ELEMENTS = 4096  # include/ppn.h
 STATUS = {0: "PPN_OK", -1: "PPN_ERR_ARG", -2: "PPN_ERR_MESH", -3: "PPN_ERR_OOM", -4: "PPN_ERR_DEVICE",
           -5: "PPN_ERR_STATE", 1: "PPN_WARN_NOT_CONVERGED", 2: "PPN_WARN_LS_FAIL"}
 
@@ -97,6 +98,7 @@ SIGNATURES = {
     "ppn_trace_get": (C.c_int, [P, C.c_int32, C.POINTER(ppn_iter_record), ip]),
     "ppn_eval_gradient": (C.c_int, [P, dp, dp]),
     "ppn_eval_element_hessians": (C.c_int, [P, dp, u8p, C.c_int32, ip, dp]),
+    "ppn_eval_element_hessians_noalloc": (C.c_int, [P, dp, u8p, C.c_int32, ip, dp]),
     "ppn_eval_hessian": (C.c_int, [P, dp, u8p, ip, ip, dp]),
     "ppn_select": (C.c_int, [P, dp, C.c_double, u8p, u8p, ip]),
     "ppn_solve": (C.c_int, [P, dp, u8p, dp, ip, ip]),

@@ -271,6 +271,16 @@ ppn_status ppn_eval_element_hessians(ppn_scene* s, const double* x, const uint8_
   });
 }
 
+ppn_status ppn_eval_element_hessians_noalloc(ppn_scene* s, const double* x,
+                                             const uint8_t* proj_mask, int32_t n,
+                                             const int32_t* ids, double* H_out) {
+  IMPL(s);
+  return guarded(s, [&] {
+    S.eval_element_hessians_noalloc(x, proj_mask, n, ids, H_out);
+    return PPN_OK;
+  });
+}
+
 ppn_status ppn_eval_hessian(ppn_scene* s, const double* x, const uint8_t* proj_mask,
                             int32_t* row_ptr, int32_t* col, double* vals) {
   IMPL(s);

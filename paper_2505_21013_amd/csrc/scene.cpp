@@ -81,6 +81,7 @@ void params_defaults(ppn_params* p) {
 Scene::Scene(hipStream_t stream, bool own, int precision)
     : st_(stream), own_stream_(own), precision_(precision) {
   params_defaults(&prm_);
+  HIPCHK(hipGetDevice(&device_));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hscal_), 64 * sizeof(double)));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hpcg_), 4 * sizeof(PcgState)));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hint_), 16 * sizeof(int32_t)));
@@ -802,30 +803,53 @@ void Scene::eval_gradient(const double* x, double* g) {
   sync();
 }
 
-void Scene::eval_element_hessians(const double* x, const uint8_t* mask, int32_t n,
-                                  const int32_t* ids, double* out) {
-  if (!out) fail("H_out must not be NULL");
+int32_t Scene::element_hessians_count(int32_t n, const int32_t* ids) const {
+  if (!loaded()) fail("no mesh loaded");
+  if (!ids) return D_.T;
+  if (n < 0) fail("n must be >= 0");
+  for (int32_t k = 0; k < n; ++k)
+    if (ids[k] < 0 || ids[k] >= D_.T) fail("element id out of range");
+  return n;
+}
+
+// The evaluation itself, with the device staging given: dids (n ids, used when
+// ids is not NULL) and dout (n 12x12 matrices).
+void Scene::eval_element_hessians_staged(const double* x, const uint8_t* mask, int32_t n,
+                                         const int32_t* ids, int32_t* dids, double* dout,
+                                         double* out) {
   stage_state(x);
   RestoreX r{this, D_, st_};
   evaluate_at_current_x();
   project_mask(mask);
-  if (!ids) n = D_.T;
+  if (ids && n > 0) HIPCHK(hipMemcpyAsync(dids, ids, size_t(n) * 4, hipMemcpyHostToDevice, st_));
+  launch_element_hessians(D_, ids ? dids : nullptr, n, dout, st_);
+  LAUNCHCHK();
+  if (n > 0) HIPCHK(hipMemcpyAsync(out, dout, size_t(n) * 144 * 8, hipMemcpyDeviceToHost, st_));
+  sync();
+}
+
+void Scene::eval_element_hessians(const double* x, const uint8_t* mask, int32_t n,
+                                  const int32_t* ids, double* out) {
+  if (!out) fail("H_out must not be NULL");
+  n = element_hessians_count(n, ids);
   int32_t* dids = nullptr;
-  if (ids) {
-    for (int32_t k = 0; k < n; ++k)
-      if (ids[k] < 0 || ids[k] >= D_.T) fail("element id out of range");
-    HIPCHK(hipMalloc(&dids, std::max<size_t>(1, size_t(n)) * 4));
-    HIPCHK(hipMemcpyAsync(dids, ids, size_t(n) * 4, hipMemcpyHostToDevice, st_));
-  }
   double* dout = nullptr;
-  HIPCHK(hipMalloc(&dout, std::max<size_t>(1, size_t(n)) * 144 * 8));
-  launch_element_hessians(D_, dids, n, dout, st_);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, size_t(n) * 144 * 8, hipMemcpyDeviceToHost, st_);
-  if (e == hipSuccess) e = hipStreamSynchronize(st_);
-  (void)hipFree(dout);
-  if (dids) (void)hipFree(dids);
-  HIPCHK(e);
+  hipError_t e = hipSuccess;
+  if (ids) e = hipMalloc(&dids, std::max<size_t>(1, size_t(n)) * 4);
+  if (e == hipSuccess) e = hipMalloc(&dout, std::max<size_t>(1, size_t(n)) * 144 * 8);
+  if (e != hipSuccess) {
+    if (dids) (void)hipFree(dids);
+    fail("hipMalloc of the element-Hessian staging failed", PPN_ERR_OOM);
+  }
+  struct Free {
+    void* a;
+    void* b;
+    ~Free() {
+      if (a) (void)hipFree(a);
+      if (b) (void)hipFree(b);
+    }
+  } release{dids, dout};
+  eval_element_hessians_staged(x, mask, n, ids, dids, dout, out);
 }
 
 void Scene::eval_hessian(const double* x, const uint8_t* mask, int32_t* row_ptr, int32_t* col,

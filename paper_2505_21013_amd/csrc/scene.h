@@ -13,6 +13,9 @@
 
 namespace ppn {
 
+// Most element Hessians one ppn_eval_element_hessians_noalloc call evaluates.
+constexpr int32_t kNoAllocMaxElements = PPN_NOALLOC_MAX_ELEMENTS;
+
 // Defaults of every parameter (the paper's values).
 void params_defaults(ppn_params* p);
 
@@ -44,6 +47,10 @@ class Scene {
   void eval_gradient(const double* x, double* g);
   void eval_element_hessians(const double* x, const uint8_t* mask, int32_t n, const int32_t* ids,
                              double* out);
+  // The same without device allocation: the staging sits in the library's
+  // fixed per-device array (at most kNoAllocMaxElements elements per call).
+  void eval_element_hessians_noalloc(const double* x, const uint8_t* mask, int32_t n,
+                                     const int32_t* ids, double* out);
   void eval_hessian(const double* x, const uint8_t* mask, int32_t* row_ptr, int32_t* col,
                     double* vals);
   void select(const double* g, double delta, const uint8_t* proj_in, uint8_t* mask, int32_t* cnt);
@@ -75,6 +82,10 @@ class Scene {
 
  private:
   void free_all();
+  // Number of matrices a call evaluates (n_tets without ids); checks the ids.
+  int32_t element_hessians_count(int32_t n, const int32_t* ids) const;
+  void eval_element_hessians_staged(const double* x, const uint8_t* mask, int32_t n,
+                                    const int32_t* ids, int32_t* dids, double* dout, double* out);
   void upload_material();
   void upload_dirichlet();
   void sync();
@@ -97,6 +108,7 @@ class Scene {
   void read_scal(int n, double* out);
 
   hipStream_t st_;
+  int device_ = 0;  // the HIP device current at creation
   bool own_stream_;
   int precision_;
   PcgBatcher* batcher_ = nullptr;

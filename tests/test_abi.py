@@ -57,3 +57,9 @@ def test_host_side_errors_without_gpu():
     assert lib.ppn_params_default(None) == -1
     assert b"out must not be NULL" in lib.ppn_last_error(None)
     assert lib.ppn_project_batch_dev(None, None, 4, 1e-8, None) == -1
+
+
+def test_noalloc_limit_matches_header():
+    from paper_2505_21013_amd import _abi
+    src = open(os.path.join(ROOT, "include", "ppn.h")).read()
+    assert int(re.search(r"#define PPN_NOALLOC_MAX_ELEMENTS (\d+)", src).group(1)) == _abi.PPN_NOALLOC_MAX_ELEMENTS
