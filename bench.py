@@ -34,12 +34,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def spmv_bytes(N, NB, fp32=False):
-    """Algorithmic bytes of one PCG matrix-product launch: every block value
-    (72 B; 36 B for the FP32 matrix of the mixed form) and column index (4 B),
-    the row pointers, the gathered z and previous direction (24 B each per
-    vertex), and the new direction and product written (24 B each per vertex;
-    the vectors are FP64 in both forms)."""
-    return (40 if fp32 else 76) * NB + 4 * (N + 1) + 4 * 24 * N
+    """Algorithmic bytes of one PCG matrix-product launch.  The symmetric matrix
+    is stored once (half storage): every stored block, the N diagonal and the
+    E = (NB - N) / 2 edge blocks, is read once (72 B; 36 B for the FP32 matrix
+    of the mixed form); every block of the full pattern costs its column and
+    value reference (8 B); each 64-row group its slot count (4 B); per vertex
+    the gathered z and previous direction are read and the new direction and
+    the product written (24 B each; the vectors are FP64 in both forms)."""
+    E = (NB - N) // 2
+    return 8 * NB + (36 if fp32 else 72) * (N + E) + 4 * ((N + 63) // 64) + 4 * 24 * N
 
 
 def measured_traffic(fp32=False):
@@ -146,7 +149,8 @@ def composite_roofline(R, precision, info, K):
     bytes per unit, as the kernels move them:
       element evaluation + assembly, per Newton iteration: 1592 B per tet
         (152 B of element data read, 720 B of slots written, slots read back
-        once by the vertex and edge passes), 261 B per vertex, 148 B per edge;
+        once by the vertex and edge passes), 261 B per vertex, 76 B per edge
+        (its block written once, its slot range pointer);
       PCG iteration: the matrix product (spmv_bytes) + the update (216 B per
         vertex: q, d, r, x and the 6-entry symmetric block-Jacobi inverse read,
         x, r and z written; 192 B with the FP32 inverse);
@@ -158,7 +162,7 @@ def composite_roofline(R, precision, info, K):
     fp32 = precision == "mixed"
     bw = HBM_PEAK_GBS * 1e9
     pcg = tot["pcg_iters"] * (spmv_bytes(N, NB, fp32) + (192 if fp32 else 216) * N) / bw
-    elem = tot["newton_iters"] * (1592 * T + 261 * N + 148 * E) / bw
+    elem = tot["newton_iters"] * (1592 * T + 261 * N + 76 * E) / bw
     ls = (tot["newton_iters"] + tot["ls_backtracks"] / 4.0) * (112 * T + 84 * N) / bw
     eig = tot["projected"] * 45.6e3 / ((157.3 if fp32 else 78.6) * 1e12)
     t_roof = (pcg + elem + ls + eig) / K

@@ -5,11 +5,14 @@
 //   vertex vectors AoS [N][3]: x, x^n, v, xhat, g, dx, r, q; PCG (z, d) records [2][N][6]
 //   vertex slots   AoS [4T][9]: corner gradient (3) + diagonal block (6)
 //   edge slots     AoS [6T][9]: off-diagonal block, row-major, global orientation
-//   BCSR values    sliced ELL: rows in groups of 64 (one wavefront), slot-major
-//                  (slot s of group g is block row s*n_groups + g); per block row
-//                  the 64 rows' blocks as four entry pairs [4][64][2] and entry 8
-//                  [64] (value_index), so every load of the matrix product is one
-//                  contiguous 1024- or 512-byte run
+//   matrix         the symmetric 3x3 block matrix stored once (half storage,
+//                  topology.h): each row owns its diagonal and upper blocks, in
+//                  sliced ELL (rows in groups of 64, one wavefront; slot-major,
+//                  half slot k of group g is block row k*n_groups + g); per block
+//                  row the 64 rows' blocks as four entry pairs [4][64][2] and
+//                  entry 8 [64] (value_index).  The product walks the full
+//                  pattern (column and value reference per slot, lower blocks
+//                  read transposed from their column's row)
 //   block-Jacobi   SoA [6][N]: inverse of each diagonal block (symmetric: upper triangle)
 //   mixed precision (only when requested): FP32 copies of the sliced-ELL
 //                  values and of the block-Jacobi inverse, three more [N][3]
@@ -66,7 +69,8 @@ struct Dev {
   int32_t Gp = 0;         // workgroups of the PCG kernels (multiple of 8; 256 rows each)
   int32_t pcg_load = -1;  // load mode of the PCG product (kLoad*), -1: chosen from the size
   int32_t n_groups = 0;   // 64-row groups of the sliced-ELL matrix
-  int64_t n_slots = 0;    // smax * n_groups (slot-major block rows)
+  int64_t n_slots = 0;    // smax * n_groups (slot-major block rows of the full pattern)
+  int64_t n_hslots = 0;   // block rows of the half storage (hsmax * n_groups + 1)
   int32_t nD = 0;         // Dirichlet vertices
   double h = 1.0 / 30.0;
   double k_dir = 1e8;
@@ -90,14 +94,14 @@ struct Dev {
   int32_t* vslot_elem = nullptr; // [4T]
   int32_t* eptr = nullptr;       // [E+1]
   int32_t* gslots = nullptr;     // [n_groups] slots of each 64-row group
-  int32_t* col = nullptr;        // [n_slots * 64] column of each (slot, lane)
-  int32_t* diag_blk = nullptr;   // [N] position (slot * 64 + lane) of the diagonal block
-  int32_t* eblk_up = nullptr;    // [E] position of block (lo, hi)
-  int32_t* eblk_lo = nullptr;    // [E] position of block (hi, lo)
+  int32_t* colref = nullptr;     // [n_slots * 64][2] per (slot, lane): column, and value
+                                 // reference (half position | kRefTranspose for a lower block)
+  int32_t* diag_blk = nullptr;   // [N] half position of the diagonal block
+  int32_t* eblk_up = nullptr;    // [E] half position of the edge block (lo, hi)
   // slots and matrix
   double* vslots = nullptr;  // [4T][9]
   double* eslots = nullptr;  // [6T][9]
-  double* vals = nullptr;    // [n_slots * 9 * 64], entry c of a block at base + 64 c
+  double* vals = nullptr;    // [n_hslots * 9 * 64] half storage, entries at value_index()
   double* pinv = nullptr;    // [6][N] upper triangle of the symmetric inverse
   uint8_t* spd_ok = nullptr; // [N]
   // Dirichlet
@@ -109,7 +113,7 @@ struct Dev {
   double* zd = nullptr;    // [2][N][6]: (z, d) records by PCG iteration parity
   double* rinf = nullptr;  // [N]
   // mixed precision (null in FP64 scenes)
-  float* vals32 = nullptr;  // [n_slots * 9 * 64]: per slot four [64] float2 entry pairs
+  float* vals32 = nullptr;  // [n_hslots * 9 * 64]: per half slot four [64] float2 entry pairs
                             // (0,1) (2,3) (4,5) (6,7), then entry 8 as [64] float
   float* pinv32 = nullptr;  // [6][N]
   double* e = nullptr;      // [N][3] correction of one refinement round
@@ -139,8 +143,8 @@ __host__ __device__ inline size_t value_index(int32_t pos, int e) {
   return e < 8 ? base + size_t(e >> 1) * 128 + 2 * lane + size_t(e & 1) : base + 512 + lane;
 }
 
-// Bytes of the FP64 sliced-ELL values (9 entries of 64 rows per slot).
-inline int64_t matrix_bytes(const Dev& D) { return D.n_slots * 9 * 64 * int64_t(sizeof(double)); }
+// Bytes of the FP64 matrix values (half storage: 9 entries of 64 rows per half slot).
+inline int64_t matrix_bytes(const Dev& D) { return D.n_hslots * 9 * 64 * int64_t(sizeof(double)); }
 
 // Load modes of the PCG product, chosen per launch from the size of the matrix
 // values (FP64, or the FP32 copy; summed over the jobs of a batched launch).
@@ -226,8 +230,8 @@ void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j
 void launch_pcg_batch_gather(const PcgJob<double>* jobs, int n, PcgState* out, hipStream_t st);
 void launch_pcg_batch_gather(const PcgJob<float>* jobs, int n, PcgState* out, hipStream_t st);
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
-// FP32 copy of the sliced-ELL values, entries paired for 8-byte loads.
-void launch_sell_to_f32(const double* src, float* dst, int64_t n_slots, hipStream_t st);
+// FP32 copy of the matrix values (n_rows block rows of 64), entries paired for 8-byte loads.
+void launch_sell_to_f32(const double* src, float* dst, int64_t n_rows, hipStream_t st);
 void launch_refine_init(const Dev& D, hipStream_t st);      // dx = 0, r = -g, |r|^2 partials
 void launch_refine_add(const Dev& D, const double* e, hipStream_t st);  // dx += e
 void launch_refine_residual(const Dev& D, hipStream_t st);  // r = -g - H dx, |r|^2 partials

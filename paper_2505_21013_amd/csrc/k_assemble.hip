@@ -50,7 +50,8 @@ __device__ inline void store_diag(const Dev& D, int i, const double hd[6]) {
   D.spd_ok[i] = ok ? 1 : 0;
 }
 
-// One edge block (lo, hi) and its transpose (hi, lo) from the edge's slots.
+// One edge block (lo, hi) from the edge's slots (the matrix stores it once;
+// the product reads it transposed for row hi).
 __device__ inline void gather_edge(const Dev& D, int k) {
   double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int t = D.eptr[k]; t < D.eptr[k + 1]; ++t) {
@@ -58,14 +59,9 @@ __device__ inline void gather_edge(const Dev& D, int k) {
 #pragma unroll
     for (int c = 0; c < 9; ++c) s[c] += sl[c];
   }
-  const int32_t pu = D.eblk_up[k], pl = D.eblk_lo[k];
+  const int32_t pu = D.eblk_up[k];
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      D.vals[value_index(pu, 3 * r + c)] = s[3 * r + c];
-      D.vals[value_index(pl, 3 * c + r)] = s[3 * r + c];
-    }
+  for (int c = 0; c < 9; ++c) D.vals[value_index(pu, c)] = s[c];
 }
 
 // Vertex pass of the full assembly: gradient, |g_i|_inf, diagonal block,
@@ -129,10 +125,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble_vertex(Dev D) {
   }
 }
 
-// Edge pass: off-diagonal block (lo, hi) and its transpose (hi, lo).  Like
+// Edge pass: off-diagonal block (lo, hi), stored once.  Like
 // the vertex pass it is component-parallel: thread (k, c) of a workgroup's
 // kEChunk edges sums entry c of edge k's slots in ascending slot order (the
-// order of gather_edge, so the same bits) and stores it in both blocks.  The
+// order of gather_edge, so the same bits) and stores it.  The
 // threads of a wavefront read consecutive doubles of their edges' contiguous
 // slot range, where one lane per edge would walk its own 72-byte records and
 // fetch each cache line several times.  One chunk per workgroup, mapped so
@@ -148,9 +144,7 @@ __global__ __launch_bounds__(kEBlock) void k_assemble_edge(Dev D, int n_wg) {
   double s = 0.0;
 #pragma unroll 4
   for (int t = D.eptr[k]; t < D.eptr[k + 1]; ++t) s += D.eslots[size_t(t) * 9 + c];
-  const int r = c / 3, cc = c % 3;
   D.vals[value_index(D.eblk_up[k], c)] = s;
-  D.vals[value_index(D.eblk_lo[k], 3 * cc + r)] = s;
 }
 
 void launch_assemble_full(const Dev& D, hipStream_t st) {

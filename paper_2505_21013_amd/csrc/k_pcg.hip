@@ -121,22 +121,22 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, cons
   pcg_init_body<M>(D, V, src, sign, logical_wg(D.Gp));
 }
 
-// The 9 entries of the block of (slot, lane).
+// The 9 entries of the block at half position pos = slot * 64 + lane of the
+// value array (value_index layout).
 // FP64: entries paired, pair k = (2k, 2k+1) at slot*576 + 128k + 2*lane, entry 8
-// at slot*576 + 512 + lane: four 16-byte loads (1024-byte runs over the
-// wavefront) and one 8-byte load.
-// kLoad == kLoadStream: the matrix is larger than the last-level cache (~300 MB
-// at 1.57M tets) and is streamed with non-temporal loads that keep it from
-// evicting the gathered (z, d) records.  Smaller matrices are read with
-// ordinary loads and stay cache-resident from one iteration to the next
-// (measured: 21 against 25 us per PCG iteration on the 122,880-tet beam; 101
-// against 91 us on the 1.57M-tet cube the other way round).  The choice
-// changes no arithmetic.
+// at slot*576 + 512 + lane: four 16-byte loads and one 8-byte load, contiguous
+// runs over a wavefront whose lanes read neighbouring positions (owned blocks;
+// lower blocks read from their column's row keep runs of up to 64 lanes).
+// kLoad == kLoadStream: the matrix is larger than the last-level cache and is
+// streamed with non-temporal loads that keep it from evicting the gathered
+// (z, d) records; smaller matrices are read with ordinary loads and stay
+// cache-resident from one iteration to the next.  The choice changes no
+// arithmetic.
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <int kLoad>
-__device__ __forceinline__ void load_block(const double* __restrict__ vals, int slot, int l,
-                                           double w[9]) {
-  const double* base = vals + size_t(slot) * (9 * kSell);
+__device__ __forceinline__ void load_block(const double* __restrict__ vals, int32_t pos, double w[9]) {
+  const double* base = vals + size_t(pos >> 6) * (9 * kSell);
+  const int l = pos & 63;
   const f64x2* v2 = reinterpret_cast<const f64x2*>(base) + l;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -148,16 +148,11 @@ __device__ __forceinline__ void load_block(const double* __restrict__ vals, int 
 }
 // FP32: entries paired, pair k = (2k, 2k+1) as a float2 at slot*576 + 2*(64k + lane)
 // for k < 4, entry 8 at slot*576 + 512 + lane: five loads of 512 / 256 bytes.
-// An FP32 matrix within the cache-resident size (148 MB of values on the
-// 1.57M-tet cube) is read with ordinary loads and stays in the 256 MB
-// last-level cache from one iteration to the next (measured there: 62 against
-// 74 us per PCG iteration with non-temporal loads); a larger one is streamed
-// with non-temporal loads like the FP64 matrix.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <int kLoad>
-__device__ __forceinline__ void load_block(const float* __restrict__ vals, int slot, int l,
-                                           float w[9]) {
-  const float* base = vals + size_t(slot) * (9 * kSell);
+__device__ __forceinline__ void load_block(const float* __restrict__ vals, int32_t pos, float w[9]) {
+  const float* base = vals + size_t(pos >> 6) * (9 * kSell);
+  const int l = pos & 63;
   const f32x2* v2 = reinterpret_cast<const f32x2*>(base) + l;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -168,6 +163,38 @@ __device__ __forceinline__ void load_block(const float* __restrict__ vals, int s
   w[8] = kLoad == kLoadStream ? __builtin_nontemporal_load(base + 8 * kSell + l) : base[8 * kSell + l];
 }
 
+// A lower block (i, j), j < i, is stored as (j, i): read it transposed.  Selects
+// rather than a branch, since the lanes of a wavefront may differ.
+template <typename M>
+__device__ __forceinline__ void orient_block(int32_t ref, M w[9]) {
+  const bool t = ref < 0;  // kRefTranspose is the sign bit
+  const M a1 = w[1], a2 = w[2], a5 = w[5];
+  w[1] = t ? w[3] : a1;
+  w[3] = t ? a1 : w[3];
+  w[2] = t ? w[6] : a2;
+  w[6] = t ? a2 : w[6];
+  w[5] = t ? w[7] : a5;
+  w[7] = t ? a5 : w[7];
+}
+
+// One component of a 3x3 block times a vector: b0 v0 + b1 v1 + b2 v2 with the
+// roundings written out (b1 v1 rounded, then b0 v0 and b2 v2 fused in turn),
+// so that the arithmetic is fixed by the source and not by which products the
+// compiler chooses to fuse.
+__device__ __forceinline__ double block_row(double b0, double b1, double b2, double v0, double v1,
+                                            double v2) {
+  return __builtin_fma(b2, v2, __builtin_fma(b0, v0, b1 * v1));
+}
+__device__ __forceinline__ float block_row(float b0, float b1, float b2, float v0, float v1,
+                                           float v2) {
+  return __builtin_fmaf(b2, v2, __builtin_fmaf(b0, v0, b1 * v1));
+}
+
+// Column and value reference of slot (slot, lane): one 8-byte load.
+__device__ __forceinline__ int2 slot_colref(const Dev& D, int slot, int l) {
+  return reinterpret_cast<const int2*>(D.colref)[size_t(slot) * kSell + l];
+}
+
 // q_i = sum over the row's slots of B d_col, d read from a plain [N][3] vector (FP64).
 __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __restrict__ src,
                                                  int g, int l, double& q0, double& q1,
@@ -176,14 +203,15 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
   q0 = q1 = q2 = 0.0;
 #pragma unroll 4
   for (int s = 0; s < S; ++s) {
-    const int slot = s * D.n_groups + g;
-    const int c = D.col[slot * kSell + l];
+    const int2 cr = slot_colref(D, s * D.n_groups + g, l);
+    const int c = cr.x;
     const double d0 = src[3 * c], d1 = src[3 * c + 1], d2 = src[3 * c + 2];
     double v[9];
-    load_block<kLoadCached>(D.vals, slot, l, v);
-    q0 += v[0] * d0 + v[1] * d1 + v[2] * d2;
-    q1 += v[3] * d0 + v[4] * d1 + v[5] * d2;
-    q2 += v[6] * d0 + v[7] * d1 + v[8] * d2;
+    load_block<kLoadCached>(D.vals, cr.y & kRefPosMask, v);
+    orient_block(cr.y, v);
+    q0 += block_row(v[0], v[1], v[2], d0, d1, d2);
+    q1 += block_row(v[3], v[4], v[5], d0, d1, d2);
+    q2 += block_row(v[6], v[7], v[8], d0, d1, d2);
   }
 }
 
@@ -197,28 +225,30 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
                                                        int g, int l, M qz[3], M qd[3]) {
   const int S = D.gslots[g];
   qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = M(0);
-  // FP64 runs best with one slot in flight per lane, streamed from HBM or from
-  // a cache-resident matrix above 64 MB, and with two for small matrices; the
-  // FP32 matrix gains from two (measured on the 1.57M-tet cube).
-  constexpr int kUnroll = sizeof(M) == 4 || kLoad == kLoadSmall ? 2 : 1;
-#pragma unroll kUnroll
+  // Two slots in flight per lane, and each slot's column and value reference
+  // loaded one slot ahead: the value loads depend on the reference (measured on
+  // the 1.57M-tet cube: 55.5 us per FP64 product against 61.0 with neither).
+  int2 nxt = S > 0 ? slot_colref(D, g, l) : make_int2(0, 0);
+#pragma unroll 2
   for (int s = 0; s < S; ++s) {
-    const int slot = s * D.n_groups + g;
-    const int c = D.col[slot * kSell + l];
+    const int2 cr = nxt;
+    if (s + 1 < S) nxt = slot_colref(D, (s + 1) * D.n_groups + g, l);
+    const int c = cr.x;
     const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
     const double2 a = p[0], b = p[1];
     const M z0 = M(a.x), z1 = M(a.y), z2 = M(b.x);
     M w[9];
-    load_block<kLoad>(vals, slot, l, w);
-    qz[0] += w[0] * z0 + w[1] * z1 + w[2] * z2;
-    qz[1] += w[3] * z0 + w[4] * z1 + w[5] * z2;
-    qz[2] += w[6] * z0 + w[7] * z1 + w[8] * z2;
+    load_block<kLoad>(vals, cr.y & kRefPosMask, w);
+    orient_block(cr.y, w);
+    qz[0] += block_row(w[0], w[1], w[2], z0, z1, z2);
+    qz[1] += block_row(w[3], w[4], w[5], z0, z1, z2);
+    qz[2] += block_row(w[6], w[7], w[8], z0, z1, z2);
     if (with_d) {
       const double2 e = p[2];
       const M d0 = M(b.y), d1 = M(e.x), d2 = M(e.y);
-      qd[0] += w[0] * d0 + w[1] * d1 + w[2] * d2;
-      qd[1] += w[3] * d0 + w[4] * d1 + w[5] * d2;
-      qd[2] += w[6] * d0 + w[7] * d1 + w[8] * d2;
+      qd[0] += block_row(w[0], w[1], w[2], d0, d1, d2);
+      qd[1] += block_row(w[3], w[4], w[5], d0, d1, d2);
+      qd[2] += block_row(w[6], w[7], w[8], d0, d1, d2);
     }
   }
 }
@@ -486,11 +516,12 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ sr
     dst[k] = float(__builtin_nontemporal_load(src + k));
 }
 
-// FP32 copy of the sliced-ELL values in the paired layout read by load_block.
+// FP32 copy of the matrix values (n_rows block rows of 64) in the paired layout
+// read by load_block.
 __global__ __launch_bounds__(kBlock) void k_sell_to_f32(const double* __restrict__ src,
-                                                        float* __restrict__ dst, int64_t n_slots) {
+                                                        float* __restrict__ dst, int64_t n_rows) {
   const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n_slots * kSell; k += stride) {
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n_rows * kSell; k += stride) {
     const int64_t slot = k / kSell;
     const int l = int(k % kSell);
     const double* v = src + slot * (9 * kSell);
@@ -506,10 +537,10 @@ __global__ __launch_bounds__(kBlock) void k_sell_to_f32(const double* __restrict
   }
 }
 
-void launch_sell_to_f32(const double* src, float* dst, int64_t n_slots, hipStream_t st) {
-  if (n_slots <= 0) return;
-  const int64_t blocks = std::min<int64_t>((n_slots * kSell + kBlock - 1) / kBlock, 8192);
-  k_sell_to_f32<<<unsigned(blocks), kBlock, 0, st>>>(src, dst, n_slots);
+void launch_sell_to_f32(const double* src, float* dst, int64_t n_rows, hipStream_t st) {
+  if (n_rows <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n_rows * kSell + kBlock - 1) / kBlock, 8192);
+  k_sell_to_f32<<<unsigned(blocks), kBlock, 0, st>>>(src, dst, n_rows);
 }
 
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st) {

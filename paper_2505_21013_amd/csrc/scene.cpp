@@ -145,6 +145,7 @@ static void geometry(Dev& D, const Topology& t) {
   // groups per 256-thread workgroup, a multiple of 8 workgroups (one per XCD).
   D.n_groups = t.n_groups;
   D.n_slots = t.n_slots;
+  D.n_hslots = t.n_hslots;
   D.Gp = ((D.n_groups + 3) / 4 + 7) / 8 * 8;
 }
 
@@ -169,13 +170,12 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
   D.vslot_elem = alloc.template get<int32_t>(4 * m);
   D.eptr = alloc.template get<int32_t>(size_t(D.E) + 1);
   D.gslots = alloc.template get<int32_t>(size_t(D.n_groups));
-  D.col = alloc.template get<int32_t>(size_t(D.n_slots) * kSell);
+  D.colref = alloc.template get<int32_t>(size_t(D.n_slots) * kSell * 2);
   D.diag_blk = alloc.template get<int32_t>(n);
   D.eblk_up = alloc.template get<int32_t>(size_t(D.E));
-  D.eblk_lo = alloc.template get<int32_t>(size_t(D.E));
   D.vslots = alloc.template get<double>(4 * m * 9);
   D.eslots = alloc.template get<double>(6 * m * 9);
-  D.vals = alloc.template get<double>(size_t(D.n_slots) * 9 * kSell);
+  D.vals = alloc.template get<double>(size_t(D.n_hslots) * 9 * kSell);
   D.pinv = alloc.template get<double>(6 * n);
   D.spd_ok = alloc.template get<uint8_t>(n);
   D.dir_idx = alloc.template get<int32_t>(n);
@@ -185,7 +185,7 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
   D.zd = alloc.template get<double>(12 * n);
   D.rinf = alloc.template get<double>(n);
   if (precision == PPN_MIXED) {
-    D.vals32 = alloc.template get<float>(size_t(D.n_slots) * 9 * kSell);
+    D.vals32 = alloc.template get<float>(size_t(D.n_hslots) * 9 * kSell);
     D.pinv32 = alloc.template get<float>(6 * n);
     D.e = alloc.template get<double>(3 * n);
     D.ri = alloc.template get<double>(3 * n);
@@ -271,12 +271,16 @@ void Scene::load_mesh(Topology&& t, const double* rest, const int32_t* tets, con
     up(D_.vslot_elem, topo_.vslot_elem.data(), 4 * m * 4);
     up(D_.eptr, topo_.eptr.data(), (size_t(D_.E) + 1) * 4);
     up(D_.gslots, topo_.gslots.data(), size_t(D_.n_groups) * 4);
-    up(D_.col, topo_.sell_col.data(), size_t(D_.n_slots) * kSell * 4);
-    up(D_.diag_blk, topo_.diag_base.data(), n * 4);
-    up(D_.eblk_up, topo_.eup_base.data(), size_t(D_.E) * 4);
-    up(D_.eblk_lo, topo_.elo_base.data(), size_t(D_.E) * 4);
-    // padding slots of the sliced-ELL values stay zero for the life of the scene
-    HIPCHK(hipMemsetAsync(D_.vals, 0, size_t(D_.n_slots) * 9 * kSell * 8, st_));
+    std::vector<int32_t> colref(2 * size_t(D_.n_slots) * kSell);
+    for (size_t k = 0; k < size_t(D_.n_slots) * kSell; ++k) {
+      colref[2 * k] = topo_.sell_col[k];
+      colref[2 * k + 1] = topo_.sell_ref[k];
+    }
+    up(D_.colref, colref.data(), colref.size() * 4);
+    up(D_.diag_blk, topo_.diag_pos.data(), n * 4);
+    up(D_.eblk_up, topo_.edge_pos.data(), size_t(D_.E) * 4);
+    // padding blocks and the zero row of the half storage stay zero for the life of the scene
+    HIPCHK(hipMemsetAsync(D_.vals, 0, size_t(D_.n_hslots) * 9 * kSell * 8, st_));
     X_.assign(rest, rest + 3 * n);
     if (E_.size() != m) {
       const double e0 = E_.empty() ? 1e5 : E_[0], n0 = nu_.empty() ? 0.45 : nu_[0];
@@ -565,7 +569,7 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
 void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
   constexpr int kMaxRounds = 8;
   constexpr double kMinInner = 1e-6;
-  launch_sell_to_f32(D_.vals, D_.vals32, int64_t(D_.n_slots), st_);
+  launch_sell_to_f32(D_.vals, D_.vals32, D_.n_hslots, st_);
   launch_to_f32(D_.pinv, D_.pinv32, int64_t(6) * D_.N, st_);
   launch_refine_init(D_, st_);
   launch_reduce_pcg(D_, kPartA, 1, st_);
@@ -860,11 +864,16 @@ void Scene::eval_hessian(const double* x, const uint8_t* mask, int32_t* row_ptr,
   project_mask(mask);
   if (vals) {
     const size_t NB = size_t(D_.NB);
-    std::vector<double> sell(size_t(D_.n_slots) * 9 * kSell);
-    HIPCHK(hipMemcpyAsync(sell.data(), D_.vals, sell.size() * 8, hipMemcpyDeviceToHost, st_));
+    std::vector<double> half(size_t(D_.n_hslots) * 9 * kSell);
+    HIPCHK(hipMemcpyAsync(half.data(), D_.vals, half.size() * 8, hipMemcpyDeviceToHost, st_));
     sync();
-    for (size_t b = 0; b < NB; ++b)
-      for (int c = 0; c < 9; ++c) vals[9 * b + c] = sell[value_index(topo_.csr_base[b], c)];
+    for (size_t b = 0; b < NB; ++b) {
+      const int32_t ref = topo_.csr_ref[b];
+      const int32_t pos = ref & kRefPosMask;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          vals[9 * b + 3 * r + c] = half[value_index(pos, ref < 0 ? 3 * c + r : 3 * r + c)];
+    }
   }
   if (row_ptr) std::copy(topo_.row_ptr.begin(), topo_.row_ptr.end(), row_ptr);
   if (col) std::copy(topo_.col.begin(), topo_.col.end(), col);

@@ -2,11 +2,13 @@
 #include "topology.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <numeric>
 
 namespace ppn {
 
-bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std::string& err) {
+bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std::string& err,
+                    int slot_order) {
   if (N <= 0 || T <= 0) {
     err = "empty mesh";
     return false;
@@ -133,8 +135,39 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
     t.eblk_lo[k] = bl;
   }
 
-  // ---- sliced-ELL layout of the same blocks, slot-major
+  // ---- half storage: each row owns [diagonal][upper blocks ascending]
   t.n_groups = (N + kSell - 1) / kSell;
+  std::vector<int32_t> hslots(t.n_groups, 0);
+  for (int32_t i = 0; i < N; ++i) hslots[i / kSell] = std::max(hslots[i / kSell], 1 + up_cnt[i]);
+  t.hsmax = *std::max_element(hslots.begin(), hslots.end());
+  t.n_hslots = int64_t(t.hsmax) * t.n_groups + 1;  // + one row of zero blocks
+  if (t.n_hslots * kSell >= (int64_t(1) << 31)) {
+    err = "matrix too large for 31-bit block positions";
+    return false;
+  }
+  t.zero_pos = int32_t((t.n_hslots - 1) * kSell);
+  auto hpos = [&](int32_t i, int32_t k) {  // half position of owned block k of row i
+    return int32_t((int64_t(k) * t.n_groups + i / kSell) * kSell + i % kSell);
+  };
+  t.diag_pos.resize(N);
+  for (int32_t i = 0; i < N; ++i) t.diag_pos[i] = hpos(i, 0);
+  t.edge_pos.resize(E);
+  t.csr_ref.resize(size_t(t.n_blocks));
+  for (int32_t i = 0; i < N; ++i) t.csr_ref[t.diag_blk[i]] = t.diag_pos[i];
+  for (int32_t k = 0; k < E; ++k) {
+    const int32_t lo = t.edge_lo[k];
+    // owned block index: 1 + rank of this edge among lo's upper edges (column order)
+    const int32_t kk = 1 + (t.eblk_up[k] - t.diag_blk[lo] - 1);
+    t.edge_pos[k] = hpos(lo, kk);
+    t.csr_ref[t.eblk_up[k]] = t.edge_pos[k];
+    t.csr_ref[t.eblk_lo[k]] = t.edge_pos[k] | kRefTranspose;
+  }
+
+  // ---- sliced-ELL form of the full pattern, slot-major, each row's blocks in
+  // CSR order or by distance |j - i| (see topology.h)
+  t.by_distance = slot_order == kSlotOrderAuto
+                      ? t.n_hslots * kSell * 9 * int64_t(sizeof(double)) > kDistanceOrderBytes
+                      : slot_order == kSlotOrderDistance;
   t.gslots.assign(t.n_groups, 0);
   for (int32_t i = 0; i < N; ++i)
     t.gslots[i / kSell] = std::max(t.gslots[i / kSell], t.row_ptr[i + 1] - t.row_ptr[i]);
@@ -145,29 +178,32 @@ bool build_topology(int32_t N, int32_t T, const int32_t* tets, Topology& t, std:
     return false;
   }
   t.sell_col.assign(size_t(t.n_slots) * kSell, 0);
-  t.csr_base.resize(size_t(t.n_blocks));
+  t.sell_ref.assign(size_t(t.n_slots) * kSell, t.zero_pos);
+  std::vector<int32_t> ord;
   for (int32_t g = 0; g < t.n_groups; ++g)
     for (int32_t l = 0; l < kSell; ++l) {
       const int32_t i = g * kSell + l;
+      if (i >= N) continue;
+      const int32_t len = t.row_ptr[i + 1] - t.row_ptr[i];
+      ord.resize(len);
+      for (int32_t q = 0; q < len; ++q) ord[q] = t.row_ptr[i] + q;
+      if (t.by_distance)
+        std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+          const int64_t da = std::abs(int64_t(t.col[a]) - i), db = std::abs(int64_t(t.col[b]) - i);
+          return da < db || (da == db && t.col[a] < t.col[b]);
+        });
       for (int32_t s = 0; s < t.smax; ++s) {
-        const int64_t slot = int64_t(s) * t.n_groups + g;
-        int32_t c = i < N ? i : 0;
-        if (i < N && s < t.row_ptr[i + 1] - t.row_ptr[i]) {
-          const int32_t k = t.row_ptr[i] + s;
+        const int64_t at = (int64_t(s) * t.n_groups + g) * kSell + l;
+        int32_t c = i, ref = t.zero_pos;
+        if (s < len) {
+          const int32_t k = ord[s];
           c = t.col[k];
-          t.csr_base[k] = int32_t(slot * kSell + l);
+          ref = t.csr_ref[k];
         }
-        t.sell_col[size_t(slot) * kSell + l] = c;
+        t.sell_col[size_t(at)] = c;
+        t.sell_ref[size_t(at)] = ref;
       }
     }
-  t.diag_base.resize(N);
-  for (int32_t i = 0; i < N; ++i) t.diag_base[i] = t.csr_base[t.diag_blk[i]];
-  t.eup_base.resize(E);
-  t.elo_base.resize(E);
-  for (int32_t k = 0; k < E; ++k) {
-    t.eup_base[k] = t.csr_base[t.eblk_up[k]];
-    t.elo_base[k] = t.csr_base[t.eblk_lo[k]];
-  }
   return true;
 }
 

@@ -13,8 +13,10 @@
 //    with lo < hi, ascending by element.  A slot holds the 3x3 off-diagonal
 //    block H_(lo,hi) in global orientation (row = lo vertex).
 //
-// The block-sparse matrix is stored full (both triangles) with columns
-// ascending in each row and the diagonal block included.
+// The block-sparse pattern is described full (both triangles, CSR with columns
+// ascending in each row and the diagonal block included), while the device
+// stores the values of the symmetric matrix once: the diagonal block of every
+// vertex and one block per edge (see the half storage below).
 #pragma once
 #include <cstdint>
 #include <string>
@@ -45,34 +47,70 @@ struct Topology {
   std::vector<int32_t> eblk_up;    // [E] block (lo, hi)
   std::vector<int32_t> eblk_lo;    // [E] block (hi, lo)
 
-  // Sliced-ELL copy of the pattern used by the device: rows in groups of 64
-  // (kSell), group g using gslots[g] = its longest row.  Storage is slot-major:
-  // slot s of group g is block row (s * n_groups + g), s < smax (the longest row
-  // of the mesh), so that wavefronts walking their groups' slots in step read
-  // neighbouring memory.  The block in (slot s, group g, lane l) has position
-  // (s * n_groups + g) * 64 + l: its column is stored there and its values at
-  // value_index(position, entry) (device.h).  Slots past a row's end hold column = the row
-  // itself and zero values; slots past a group's end are never read.
+  // Sliced-ELL form of the full pattern walked by the matrix product: rows in
+  // groups of 64 (kSell), group g using gslots[g] = its longest row.  Storage is
+  // slot-major: slot s of group g is block row (s * n_groups + g), s < smax (the
+  // longest row of the mesh), so that wavefronts walking their groups' slots in
+  // step read neighbouring memory.  The order of a row's slots fixes the
+  // product's accumulation order.  Matrices whose stored values exceed
+  // kDistanceOrderBytes hold each row's blocks by distance |j - i| (the
+  // diagonal first; j = i - d before j = i + d): the two reads of a stored
+  // block, by its owner row and transposed by its partner row, then fall at
+  // about the same slot of the concurrently running rows and meet in the L2.
+  // Smaller matrices, which stay in the cache anyway, keep the CSR order
+  // (columns ascending).  Per (slot s,
+  // group g, lane l), at (s * n_groups + g) * 64 + l: the column (sell_col) and
+  // the reference of the block's values (sell_ref).  Slots past a row's end
+  // hold column = the row itself and refer to a block of zeros; slots past a
+  // group's end are never read.
   int32_t n_groups = 0;
   int32_t smax = 0;
   int64_t n_slots = 0;              // smax * n_groups block rows of 64
   std::vector<int32_t> gslots;      // [n_groups]
   std::vector<int32_t> sell_col;    // [n_slots * 64]
-  // Block positions slot * 64 + lane (the block's values are addressed in
-  // 64-bit arithmetic from the position: value_index() in device.h).
-  std::vector<int32_t> csr_base;    // [NB] position of each CSR block
-  std::vector<int32_t> diag_base;   // [N]
-  std::vector<int32_t> eup_base;    // [E]
-  std::vector<int32_t> elo_base;    // [E]
+  std::vector<int32_t> sell_ref;    // [n_slots * 64]
+
+  // Half storage of the values.  Row i owns its diagonal block and its upper
+  // blocks (i, j), j > i: 1 + (upper count) blocks, kept in a sliced-ELL layout
+  // of their own, slot-major over "half slots" (hslots per group = its longest
+  // owned list, hsmax over the mesh); owned block k of row i = 64 g + l sits at
+  // position (k * n_groups + g) * 64 + l, and its values at value_index(position,
+  // entry) (device.h): a wavefront's lanes at the same slot read neighbouring
+  // positions wherever their rows share a neighbour pattern (the interior of
+  // a grid).  A lower
+  // block (i, j), j < i, refers to the position of (j, i) in row j with
+  // kRefTranspose set: its values are read transposed.  One extra half row of
+  // 64 zero blocks (position zero_pos) serves the padding slots.
+  bool by_distance = false;         // slot order: by distance, else CSR
+  int32_t hsmax = 0;
+  int64_t n_hslots = 0;             // hsmax * n_groups half rows of 64, plus the zero row
+  int32_t zero_pos = 0;             // position of a zero block
+  // References: a half position, with kRefTranspose set for a lower block.
+  std::vector<int32_t> csr_ref;     // [NB] reference of each CSR block
+  std::vector<int32_t> diag_pos;    // [N] half position of each diagonal block
+  std::vector<int32_t> edge_pos;    // [E] half position of each edge block (lo, hi)
 };
 
+// Set in a reference when the block is read transposed (it is stored as the
+// upper block of the column's row).
+constexpr int32_t kRefTranspose = int32_t(0x80000000u);
+constexpr int32_t kRefPosMask = 0x7fffffff;
+
 constexpr int kSell = 64;  // rows per sliced-ELL group (one wavefront)
+
+// Stored FP64 matrix values above which the slots are ordered by distance
+// (measured on the 1.57M-tet cube, 158 MB: 55.5 against 62.0 us per FP64
+// product with the CSR order).
+constexpr int64_t kDistanceOrderBytes = int64_t(64) << 20;
+
+// Slot order requested from build_topology: chosen from the size, or forced.
+constexpr int kSlotOrderAuto = -1, kSlotOrderCsr = 0, kSlotOrderDistance = 1;
 
 // Builds the topology from tets [T][4] (AoS, 0-based).  Returns false and sets
 // err when an index is out of range, an element repeats a vertex, a vertex
 // belongs to no element, or the mesh exceeds the 32-bit index limits.
 bool build_topology(int32_t n_verts, int32_t n_tets, const int32_t* tets, Topology& out,
-                    std::string& err);
+                    std::string& err, int slot_order = kSlotOrderAuto);
 
 // Vertex orders of locality_order.
 constexpr int32_t kOrderPencil = 0;  // banded sweep across the longest axis

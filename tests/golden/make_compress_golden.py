@@ -9,8 +9,12 @@ positions after every step.  Calls only the oracle and the scene generator.
 The record is rewritten after every step, so a long run leaves a usable prefix.
 Run from the repository root, one process per (n, mode):
 
-    python tests/golden/make_compress_golden.py 64 PPN 2     # the 1,572,864-tet cube, steps 1-2
-    python tests/golden/make_compress_golden.py 32 PPN 46    # 196,608 tets, through the breakdown
+    python tests/golden/make_compress_golden.py 64 PPN 2 ids  # the 1,572,864-tet cube, steps 1-2
+    python tests/golden/make_compress_golden.py 32 PPN 46     # 196,608 tets, through the breakdown
+
+With "ids", every Newton iteration also stores its projected element ids
+(ascending), so that a run can count the elements on which its projected set
+differs from the oracle's.
 """
 import json
 import os
@@ -33,7 +37,7 @@ def fingerprint(ids):
     return [int(ids.size), int(ids.sum()), int((ids * ids).sum())]
 
 
-def main(n, mode, steps):
+def main(n, mode, steps, with_ids=False):
     sc = cube_compress(n=n, n_steps=50, ramp_steps=50)
     rng = np.random.default_rng(n)
     sample = np.sort(rng.choice(sc.n_verts, SAMPLE, replace=False))
@@ -51,7 +55,8 @@ def main(n, mode, steps):
             res_l2=st.res_l2, res_inf=st.res_inf, oracle_seconds=now - t_last[0],
             iters=[dict(g_l2=r["g_l2"], g_inf=r["g_inf"], dx_inf=r.get("dx_inf"), gamma=r.get("gamma"),
                         rounds=len(r["rounds"]),
-                        mask=fingerprint(r.get("projected_idx", np.zeros(0, np.int64))))
+                        mask=fingerprint(r.get("projected_idx", np.zeros(0, np.int64))),
+                        **({"ids": r.get("projected_idx", np.zeros(0, np.int64)).tolist()} if with_ids else {}))
                    for r in st.trace],
             x_sample=s.x[sample].tolist()))
         t_last[0] = now
@@ -66,4 +71,4 @@ def main(n, mode, steps):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]), sys.argv[2], int(sys.argv[3]))
+    main(int(sys.argv[1]), sys.argv[2], int(sys.argv[3]), len(sys.argv) > 4 and sys.argv[4] == "ids")

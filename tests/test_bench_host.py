@@ -9,10 +9,14 @@ import bench
 
 
 def test_product_bytes_per_launch():
-    # 64^3 compressed cube: N = 274,625 vertices, NB = 4,018,753 blocks
-    assert bench.spmv_bytes(274625, 4018753, False) == 76 * 4018753 + 4 * 274626 + 96 * 274625
-    assert bench.spmv_bytes(274625, 4018753, True) == 40 * 4018753 + 4 * 274626 + 96 * 274625
-    assert round(bench.spmv_bytes(274625, 4018753, False) / 1e6, 1) == 332.9
+    # 64^3 compressed cube: N = 274,625 vertices, E = 1,872,064 edges,
+    # NB = N + 2E = 4,018,753 blocks, 4,292 groups of 64 rows
+    N, E = 274625, 1872064
+    NB = N + 2 * E
+    assert NB == 4018753
+    assert bench.spmv_bytes(N, NB, False) == 8 * NB + 72 * (N + E) + 4 * 4292 + 96 * N
+    assert bench.spmv_bytes(N, NB, True) == 8 * NB + 36 * (N + E) + 4 * 4292 + 96 * N
+    assert round(bench.spmv_bytes(N, NB, False) / 1e6, 1) == 213.1
 
 
 def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):

@@ -167,8 +167,9 @@ def test_engine_request_record_is_freed_after_its_wait():
 
 def test_engine_oversized_scene_is_refused():
     sc = _small_scenes(1)[0]
-    with Engine(n_workers=1, mem_budget_bytes=1 << 20) as e:
+    with Engine(n_workers=1, mem_budget_bytes=1 << 16) as e:
         sid = e.add_scene(sc)
+        assert e.ppn_engine_scene_footprint(sid) > 1 << 16
         r = e.ppn_engine_wait(e.ppn_engine_submit(sid, "PPN", sc.targets(1)))
     assert r["status"] == "PPN_ERR_OOM"
 
