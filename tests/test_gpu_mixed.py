@@ -2,23 +2,25 @@
 
 In this form the eigensolves and the PCG iterations run in FP32 while the
 gradient, the energies, the assembly and each solve's refinement residual stay
-FP64.  The bar, per result:
+FP64.  The bars, per result:
   * element projections within 2e-5 of the element matrix's magnitude (FP32
     Jacobi), still positive semidefinite to that level;
   * every linear solve meets the FP64 bound |H dx + g| <= rtol |g| on the
     oracle's own operator (the refinement guarantees it);
-  * whole time steps: positions within 1e-6 of the bounding-box diagonal of
-    the oracle's trajectory; the Newton residual the step reports (FP64) within
-    1e-8 of the oracle's residual at the same state, both relative to the
-    step's initial residual (a converged residual is a sum of large cancelling
-    terms, so relative to itself it carries the FP64 rounding of those terms
-    amplified by their ratio to it); the projected-set mismatch
-    rate against the oracle, and the difference of the two trajectories' final
-    residuals (relative to the step's initial residual), printed and bounded.
-    The trajectories' final residuals are not held to 1e-8: both runs stop on
-    |dx|_inf after inexact solves (|r| <= 1e-4 |g|) whose Krylov iterates differ
-    once the arithmetic differs, so the last iterate of a step differs at the
-    level of the stopping tolerance.
+  * whole time steps, trajectory against trajectory: positions within 1e-6 of
+    the bounding-box diagonal; the Newton residual each step ends with against
+    the oracle's own final residual of that step, relative to the step's
+    initial residual (R30), printed beside the same figure for the FP64 GPU
+    form and held to 1e-8 where the scene meets it, or to the measured value
+    with the shortfall stated; the projected-set mismatch rate (summed
+    symmetric difference of the per-iteration projected sets over their
+    union), printed and bounded, on scenes that project.
+  Both runs stop on |dx|_inf after inexact solves (|r| <= 1e-4 |g|): once the
+  arithmetic differs, the Krylov iterates differ, so the last iterate of a step
+  differs at the level of the stopping tolerance.  On the 6^3 jittered cube
+  this puts the trajectory residual difference at a few 1e-8 of the initial
+  residual, above the 1e-8 asked for; on the 1.57M-tet cube it is about 1e-12
+  (tests/test_gpu_cube64_golden.py).
 """
 import json
 import os
@@ -106,9 +108,18 @@ def _mask_mismatch(o_trace, g_trace):
     return diff, union
 
 
+# Trajectory residual bar per scene: 1e-8 of the initial residual (the stated
+# accuracy), except where the measured difference is above it; there the bar is
+# the measured value rounded up, and the shortfall is the result: the 6^3
+# jittered cube ends its steps 3.5e-8 (6.2e-8 renumbered) of the initial
+# residual away from the oracle's final residual in PDN and PPN, while the FP64
+# GPU form stays within 4e-14 there.
+RES_BAR = {"cube6_jitter": 1e-7, "cube6_jitter_renum5": 1e-7, "cube6_compress": 1e-8}
+
+
 @pytest.mark.parametrize("mode", ["PN", "PDN", "PPN"])
 def test_mixed_cube6_jitter_20_steps(mode):
-    _mixed_against_oracle(config(0), mode)
+    _mixed_against_oracle(config(0), mode, RES_BAR["cube6_jitter"])
 
 
 @pytest.mark.parametrize("mode", ["PN", "PPN"])
@@ -116,14 +127,21 @@ def test_mixed_renumbered_cube6_jitter_20_steps(mode):
     """The same scene numbered at random (vertices, elements, local orders):
     the FP32 matrix conversion and product then work on 64-row groups of
     mixed row lengths with scattered columns, and must meet the same bars."""
-    _mixed_against_oracle(renumbered(config(0), seed=5), mode)
+    _mixed_against_oracle(renumbered(config(0), seed=5), mode, RES_BAR["cube6_jitter_renum5"])
 
 
-def _mixed_against_oracle(sc, mode):
-    orc_x = []
-    _, ost = oracle.run_scene(sc, mode, n_steps=sc.n_steps, trace=True,
-                              callback=lambda n, s, st: orc_x.append(s.x.copy()))
-    gpu = gpu_scene(sc, trace=True, precision=PPN_MIXED)
+@pytest.mark.parametrize("mode", ["PDN", "PPN"])
+def test_mixed_compressed_cube6_projects(mode):
+    """A 6^3 cube squashed over 8 steps: PPN runs inner rounds and PDN projects
+    every element after detecting indefiniteness, so the projected-set mismatch
+    rate is measured on projections that happen."""
+    sc = cube_compress(n=6, n_steps=8, ramp_steps=8)
+    union = _mixed_against_oracle(sc, mode, RES_BAR["cube6_compress"])
+    assert union > 0
+
+
+def _trajectory(sc, mode, precision):
+    gpu = gpu_scene(sc, trace=True, precision=precision)
     gstate, gtr = [(sc.x0.copy(), sc.v0.copy())], []
 
     def cb(n, s, st):
@@ -131,9 +149,18 @@ def _mixed_against_oracle(sc, mode):
         gtr.append(s.ppn_trace())
     gst = run_steps(gpu, sc, mode, sc.n_steps, callback=cb)
     gpu.close()
+    return gst, gstate, gtr
+
+
+def _mixed_against_oracle(sc, mode, res_bar):
+    orc_x = []
+    _, ost = oracle.run_scene(sc, mode, n_steps=sc.n_steps, trace=True,
+                              callback=lambda n, s, st: orc_x.append(s.x.copy()))
+    gst, gstate, gtr = _trajectory(sc, mode, PPN_MIXED)
+    f64, _, _ = _trajectory(sc, mode, 0)
     diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
     diff = union = 0
-    worst_pos = worst_res = worst_traj = 0.0
+    worst_pos = worst_eval = worst_traj = worst_traj64 = 0.0
     for n in range(sc.n_steps):
         o, g = ost[n], gst[n]
         tag = f"{mode} step {n + 1}"
@@ -141,24 +168,30 @@ def _mixed_against_oracle(sc, mode):
         assert g["refine_rounds"] >= g["solves"], tag
         x, _ = gstate[n + 1]
         worst_pos = max(worst_pos, float(np.max(np.abs(x - orc_x[n]))) / diag)
-        # the oracle's residual at the state the GPU step ended in
+        # the residual the step reports is the FP64 gradient norm at its own
+        # final state (the oracle's gradient there, evaluated independently)
         st = oracle_stepper(sc, step=n + 1)
         xp, vp = gstate[n]
         st.xhat = predictor(xp, vp, st.h, st.gravity)
         res = float(np.linalg.norm(st.gradient(x)))
-        worst_res = max(worst_res, abs(g["res_l2"] - res) / g["res0_l2"])
+        worst_eval = max(worst_eval, abs(g["res_l2"] - res) / g["res0_l2"])
+        # trajectory against trajectory: the step's final residual against the
+        # oracle's own final residual of that step (R30), mixed and FP64 forms
         worst_traj = max(worst_traj, abs(g["res_l2"] - o.res_l2) / o.res0_l2)
+        worst_traj64 = max(worst_traj64, abs(f64[n]["res_l2"] - o.res_l2) / o.res0_l2)
         d, u = _mask_mismatch(o.trace, gtr[n])
         diff += d
         union += u
     rate = diff / max(union, 1)
-    print(f"\nmixed {mode}: max position error {worst_pos:.2e} diag, reported residual vs oracle "
-          f"{worst_res:.2e} res0, trajectory residual difference {worst_traj:.2e} res0, projected-set "
-          f"mismatch {rate:.4f} ({diff}/{union})")
+    print(f"\nmixed {sc.name} {mode}: positions {worst_pos:.2e} of the diagonal; final residual against "
+          f"the oracle's {worst_traj:.2e} res0 (FP64 GPU form {worst_traj64:.2e} res0; bar {res_bar:.0e}); "
+          f"projected-set mismatch {rate:.2e} ({diff}/{union}); reported residual vs the FP64 gradient at "
+          f"the same state {worst_eval:.2e} res0")
     assert worst_pos <= 1e-6, worst_pos
-    assert worst_res <= 1e-8, worst_res
-    assert worst_traj <= 1e-6, worst_traj
+    assert worst_eval <= 1e-10, worst_eval
+    assert worst_traj <= res_bar, worst_traj
     assert rate <= 0.05, rate
+    return union
 
 
 def test_mixed_cube16_schedule_against_oracle_record():
@@ -178,7 +211,7 @@ def test_mixed_cube16_schedule_against_oracle_record():
     err = float(np.max(np.abs(x[sample] - np.array(ref["final_x_sample"])))) / diag
     print(f"\nmixed cube16 PPN: trajectory residual difference {worst_traj:.2e} res0, final "
           f"position error {err:.2e} diag")
-    assert worst_traj <= 1e-6, worst_traj
+    assert worst_traj <= 1e-8, worst_traj
     assert err <= 1e-6, err
 
 
@@ -227,3 +260,56 @@ def test_mixed_streamed_fp32_matrix_meets_fp64_residual():
     assert np.linalg.norm(r) <= 1e-4 * np.linalg.norm(g) * (1 + 1e-3)
     assert g @ dx < 0
     gpu.close()
+
+
+def test_mixed_beam_twist_against_oracle_record():
+    """The twisted beam (122,880 tets) over its 100-step schedule in the mixed
+    form against the oracle's PPN record (tests/golden/beam_twist_PPN.json):
+    per step the final residual against the oracle's (R30) and the Newton and
+    projection counts, per Newton iteration whether the projected set equals the
+    oracle's (fingerprints), sampled positions after steps 25, 50, 75 and 100.
+    Printed: the largest residual difference over the steps whose counts match
+    the oracle's, the steps whose counts differ, the share of Newton iterations
+    whose projected set differs, the position errors."""
+    path = os.path.join(HERE, "golden", "beam_twist_PPN.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written")
+    gold = json.load(open(path))
+    sc = config(1)
+    sample = np.array(gold["sample_vertices"])
+    gpu = gpu_scene(sc, trace=True, precision=PPN_MIXED)
+    masks, snaps = [], {}
+
+    def fp(ids):
+        ids = np.asarray(ids, dtype=np.int64)
+        return [int(ids.size), int(ids.sum()), int((ids * ids).sum())]
+
+    def cb(n, s, st):
+        masks.append([fp(r["projected_ids"]) for r in s.ppn_trace()])
+        if str(n) in gold["x_sample"]:
+            snaps[str(n)] = s.ppn_get_positions()[sample]
+    stats = run_steps(gpu, sc, "PPN", len(gold["steps"]), callback=cb)
+    gpu.close()
+    diag = float(np.linalg.norm(sc.X.max(0) - sc.X.min(0)))
+    differ, worst_traj, n_iter, iter_mism = [], 0.0, 0, 0
+    for n, (g, o) in enumerate(zip(stats, gold["steps"])):
+        assert g["status"] in ("PPN_OK", "PPN_WARN_NOT_CONVERGED"), (n + 1, g["status"])
+        if (g["newton_iters"], g["projected"]) != (o["newton_iters"], o["projected"]):
+            differ.append((n + 1, g["newton_iters"], o["newton_iters"], g["projected"], o["projected"]))
+            continue
+        worst_traj = max(worst_traj, abs(g["res_l2"] - o["res_l2"]) / o["res0_l2"])
+        for a, b in zip(masks[n], o["masks"]):
+            n_iter += 1
+            iter_mism += a != b
+    errs = {k: float(np.max(np.abs(snaps[k] - np.array(v)))) / diag for k, v in gold["x_sample"].items()}
+    print(f"\nmixed beam PPN: steps whose counts differ from the oracle's (step, Newton, oracle's, projected, "
+          f"oracle's) {differ}; on the others: final residual against the oracle's {worst_traj:.2e} res0, "
+          f"Newton iterations whose projected set differs {iter_mism}/{n_iter}; positions "
+          f"{', '.join(f'step {k} {v:.2e}' for k, v in errs.items())} of the diagonal")
+    # Step 95, where PN and PDN reach the iteration cap, is the one whose counts
+    # move with the rounding of the solves (the FP64 form matches it exactly).
+    assert [d[0] for d in differ] in ([], [95]), differ
+    assert worst_traj <= 1e-8, worst_traj
+    assert iter_mism <= 0.01 * n_iter, (iter_mism, n_iter)
+    for k, v in errs.items():
+        assert v <= 1e-6 or int(k) >= 95, (k, v)
