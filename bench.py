@@ -62,10 +62,20 @@ def measured_traffic(fp32=False):
     return value if have == want else None
 
 
+# The extrapolation checked against whole oracle time steps of the 1.57M-tet
+# cube (tests/golden/cube64_compress_PPN.json records each step's oracle time;
+# both were taken on the same host, an Intel Xeon at 2.7 GHz): the sampled
+# costs with those steps' counts give 730.2 and 423.0 s against 563.6 and
+# 326.5 s timed, i.e. the extrapolation overestimates a step by 1.30x.
+EXTRAPOLATION_CHECK = {"extrapolated_over_timed": 1.30, "steps": "1 and 2 of the 1.57M-tet cube",
+                       "host": "Intel(R) Xeon(R) Processor @ 2.70GHz, one core"}
+
+
 def cpu_baseline(cfg, per_step_counts):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-m", "oracle.baseline", "--config", str(cfg)], cwd=ROOT,
-                       capture_output=True, text=True, env=env, timeout=600)
+    core = min(os.sched_getaffinity(0))
+    r = subprocess.run([sys.executable, "-m", "oracle.baseline", "--config", str(cfg), "--cpu", str(core)],
+                       cwd=ROOT, capture_output=True, text=True, env=env, timeout=600)
     if r.returncode != 0:
         return {"error": r.stderr[-500:]}
     c = json.loads(r.stdout.strip().splitlines()[-1])
@@ -77,7 +87,8 @@ def cpu_baseline(cfg, per_step_counts):
                        f"Hessians, {c['pcg_iters_timed']} PCG iterations on the partial operator and one "
                        f"line-search energy pass, timed ({c['wall_s']:.1f} s) and scaled per element / per "
                        f"nonzero to the full mesh with the timed run's mean per-step counts"),
-            "s_per_step": sec}
+            "s_per_step": sec, "cpu_model": c.get("cpu_model"), "pinned_core": c.get("pinned_core"),
+            "host_cpus": c.get("host_cpus"), "extrapolation_check": EXTRAPOLATION_CHECK}
 
 
 def run_form(a, precision, torch, np):
@@ -86,7 +97,8 @@ def run_form(a, precision, torch, np):
     from scenes import config, cube_compress
     sc = cube_compress(n=a.cells) if a.cells and a.config == 2 else config(a.config)
     stream = torch.cuda.current_stream().cuda_stream
-    s = scene_from(sc, stream=stream, precision=PPN_MIXED if precision == "mixed" else PPN_FP64)
+    s = scene_from(sc, stream=stream, precision=PPN_MIXED if precision == "mixed" else PPN_FP64,
+                   params=dict(use_graphs=0) if a.no_graphs else None)
     info = s.ppn_scene_info()
     for n in range(1, a.warmup + 1):
         s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
@@ -188,10 +200,11 @@ def roofline(R, precision, info, cfg):
             "launches": tot["n_spmv"]}
 
 
-def _engine_scenes(engine, scenes, precision):
+def _engine_scenes(engine, scenes, precision, graphs=True):
     from paper_2505_21013_amd import PPN_MIXED
     t = time.perf_counter()
-    ids = [engine.add_scene(sc, precision=PPN_MIXED if precision == "mixed" else 0) for sc in scenes]
+    prm = None if graphs else dict(use_graphs=0)
+    ids = [engine.add_scene(sc, precision=PPN_MIXED if precision == "mixed" else 0, params=prm) for sc in scenes]
     print(f"registered {len(ids)} scenes in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     return ids
 
@@ -214,13 +227,15 @@ def run_batch(a):
            "config": {"workload": f"64 rotated blocks, {sum(s.n_tets for s in scenes)} tets in total "
                                   f"({min(s.n_tets for s in scenes)}..{max(s.n_tets for s in scenes)} per "
                                   f"scene), steps 1..{K}, PPN", "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")}}
-    runs = [("workers_1", 1, False), (f"workers_{a.workers}", a.workers, False),
-            ("batched_pcg", len(scenes), True)]
-    for key, workers, batched in runs:
+    # (key, workers, batching: 0 none / 1 PCG / 2 PCG + evaluation and line search, graphs)
+    runs = [("workers_1", 1, 0, True), (f"workers_{a.workers}_no_graphs", a.workers, 0, False),
+            (f"workers_{a.workers}", a.workers, 0, True), ("batched_pcg", len(scenes), 1, True),
+            ("batched_pcg_eval", len(scenes), 2, True)]
+    for key, workers, batched, graphs in runs:
         with Engine(n_workers=workers) as e:
             if batched:
-                e.ppn_engine_set_pcg_batching(True)
-            ids = _engine_scenes(e, scenes, "mixed")
+                e.ppn_engine_set_batching(pcg=True, evaluation=batched == 2)
+            ids = _engine_scenes(e, scenes, "mixed", graphs)
             warm = [e.ppn_engine_submit(sid, "PPN", sc.targets(1)) for sc, sid in zip(scenes, ids)]
             for r in warm:
                 e.ppn_engine_wait(r)
@@ -232,7 +247,8 @@ def run_batch(a):
             el = time.perf_counter() - t0
             info = e.ppn_engine_get_info()
             ok = all(r["status"] in ("PPN_OK",) for r in res)
-            out[key] = {"workers": workers, "pcg_batching": batched, "value": len(reqs) / el,
+            out[key] = {"workers": workers, "pcg_batching": batched >= 1, "eval_batching": batched == 2,
+                        "graphs": graphs and batched < 2, "value": len(reqs) / el,
                         "elapsed_s": el, "all_converged": ok,
                         "newton_iters": sum(r["newton_iters"] for r in res),
                         "pcg_iters": sum(r["pcg_iters"] for r in res),
@@ -241,8 +257,11 @@ def run_batch(a):
             if batched:
                 out[key]["pcg_chunks"] = info["pcg_batches"]
                 out[key]["pcg_solves"] = info["pcg_batched_solves"]
+            if batched == 2:
+                out[key]["eval_launches"] = info["eval_launches"]
+                out[key]["eval_phases"] = info["eval_batched_phases"]
             print(f"batch {key}: {len(reqs) / el:.1f} steps/s", file=sys.stderr, flush=True)
-    out["value"] = max(out[k]["value"] for k, _, _ in runs)
+    out["value"] = max(out[k]["value"] for k, _, _, _ in runs)
     out["speedup_vs_one_worker"] = out["value"] / out["workers_1"]["value"]
     return out
 
@@ -408,6 +427,8 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"],
                     help="fp64 or mixed alone, or both (FP64 headline, mixed reported beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="plain launches instead of the captured evaluation graph (use_graphs = 0)")
     ap.add_argument("--cells", type=int, default=None,
                     help="compressed cube of N^3 cells instead of 64^3 (size studies: no CPU baseline, and no "
                          "counter traffic, which was measured at 64^3)")

@@ -73,7 +73,7 @@ typedef enum {
  * alpha 0.5, beta 2, eps_delta 1e-12 (Sec. 4); eps_clamp 1e-8, PCG relative
  * tolerance 1e-4, PDN countdown 4, velocity tolerance 1e-3 m/s (Sec. 5.1).
  * The remaining values are readings: pcg_maxit 10000, newton_maxit 100,
- * Armijo c 1e-4 with at most 30 halvings, k_dirichlet 1e8 N/m. */
+ * Armijo c 1e-4 with at most 30 halvings, k_dirichlet 1e8 N/m; use_graphs 1. */
 typedef struct {
   double alpha;         /* tightening factor, 0 < alpha < 1 */
   double beta;          /* release factor, >= 1 */
@@ -94,7 +94,10 @@ typedef struct {
                             2 streamed: forces how the PCG product of this scene's own solves loads
                             the matrix.  Every mode gives the same bits; for tuning and tests.
                             Batched engine launches always choose from the summed size. */
-  int32_t reserved;      /* 0 */
+  int32_t use_graphs;    /* 1 (default): a scene stepped alone runs the kernels of each Newton
+                            iteration's evaluation (element quantities, assembly, gradient
+                            norms) as one HIP graph captured at its first use; 0: plain
+                            launches.  The same kernels either way, so the same bits. */
 } ppn_params;
 
 /* Statistics of one time step. */
@@ -389,6 +392,8 @@ typedef struct {
   int32_t resident_scenes, n_scenes, n_workers, pending;
   int64_t pcg_batches;         /* shared-launch PCG chunks run (batching on) */
   int64_t pcg_batched_solves;  /* solves carried by them */
+  int64_t eval_launches;       /* shared evaluation / line-search phases run (PPN_BATCH_EVAL) */
+  int64_t eval_batched_phases; /* scene phases carried by them */
 } ppn_engine_info;
 
 /* Create an engine on the current HIP device.  mem_budget_bytes <= 0 means 90%
@@ -427,6 +432,19 @@ ppn_status ppn_engine_get_info(ppn_engine* e, ppn_engine_info* out);
  * Results are unchanged bit for bit.  Off by default.  PPN_ERR_STATE unless
  * the engine is idle. */
 ppn_status ppn_engine_set_pcg_batching(ppn_engine* e, int32_t enable);
+/* Shared launches across the scenes stepped at the same time (the per-element
+ * parallelism of Sec. 4.1 carried across scenes): PPN_BATCH_PCG batches the
+ * PCG solves as ppn_engine_set_pcg_batching(e, 1) does; adding PPN_BATCH_EVAL
+ * also hands each Newton iteration's evaluation (element energies, gradients
+ * and Hessians, assembly, gradient norms) and each line-search launch to one
+ * thread that runs the phases of every scene waiting at that moment as one
+ * launch per kernel over a table of the scenes.  Results are unchanged bit for
+ * bit (every scene runs the same kernels with the same scene-local indices).
+ * flags: 0, PPN_BATCH_PCG or PPN_BATCH_PCG | PPN_BATCH_EVAL (PPN_ERR_ARG
+ * otherwise); PPN_ERR_STATE unless the engine is idle. */
+#define PPN_BATCH_PCG 1
+#define PPN_BATCH_EVAL 2
+ppn_status ppn_engine_set_batching(ppn_engine* e, int32_t flags);
 
 #ifdef __cplusplus
 }

@@ -80,15 +80,35 @@ def per_step_seconds(c, counts):
             + counts["ls_trials"] * c["t_ls_per_elem"] * T)
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), else the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--n-sample", type=int, default=786432)
+    ap.add_argument("--cpu", type=int, default=None, help="pin the process to this core")
     a = ap.parse_args()
+    if a.cpu is not None:
+        os.sched_setaffinity(0, {a.cpu})
     from scenes import config
     t = time.perf_counter()
     c = sample_costs(config(a.config), n_sample=a.n_sample)
     c["wall_s"] = time.perf_counter() - t
+    c["cpu_model"] = cpu_model()
+    c["pinned_core"] = a.cpu
+    c["cores_allowed"] = sorted(os.sched_getaffinity(0))
+    c["host_cpus"] = os.cpu_count()
     print(json.dumps(c))
 
 

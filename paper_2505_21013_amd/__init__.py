@@ -403,6 +403,12 @@ class Engine:
     def ppn_engine_set_pcg_batching(self, enable=True):
         _check(_abi.lib().ppn_engine_set_pcg_batching(self._h, int(bool(enable))))
 
+    def ppn_engine_set_batching(self, pcg=True, evaluation=False):
+        """Shared launches across scenes: PCG solves, and with evaluation=True the
+        per-iteration evaluation and line-search phases too."""
+        flags = (_abi.PPN_BATCH_PCG if pcg else 0) | (_abi.PPN_BATCH_EVAL if evaluation else 0)
+        _check(_abi.lib().ppn_engine_set_batching(self._h, flags))
+
     def ppn_engine_get_info(self):
         i = ppn_engine_info()
         _check(_abi.lib().ppn_engine_get_info(self._h, C.byref(i)))

@@ -10,6 +10,7 @@ PPN_FP64, PPN_MIXED = 0, 1
 PPN_STOP_VEL, PPN_STOP_GRAD_REL = 0, 1
 PPN_ORDER_PENCIL, PPN_ORDER_MORTON = 0, 1
 PPN_NOALLOC_MAX_ELEMENTS = 4096  # include/ppn.h
+PPN_BATCH_PCG, PPN_BATCH_EVAL = 1, 2
 STATUS = {0: "PPN_OK", -1: "PPN_ERR_ARG", -2: "PPN_ERR_MESH", -3: "PPN_ERR_OOM", -4: "PPN_ERR_DEVICE",
           -5: "PPN_ERR_STATE", 1: "PPN_WARN_NOT_CONVERGED", 2: "PPN_WARN_LS_FAIL"}
 
@@ -20,7 +21,7 @@ class ppn_params(C.Structure):
                 ("pdn_countdown", C.c_int32), ("stop_mode", C.c_int32), ("newton_maxit", C.c_int32),
                 ("stop_tol", C.c_double), ("armijo_c", C.c_double), ("ls_maxit", C.c_int32),
                 ("eig_mirror", C.c_int32), ("k_dirichlet", C.c_double), ("pcg_load_mode", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("use_graphs", C.c_int32)]
 
 
 class ppn_step_stats(C.Structure):
@@ -62,7 +63,8 @@ class ppn_engine_info(C.Structure):
     _fields_ = [("budget_bytes", C.c_int64), ("resident_bytes", C.c_int64), ("admissions", C.c_int64),
                 ("evictions", C.c_int64), ("resident_scenes", C.c_int32), ("n_scenes", C.c_int32),
                 ("n_workers", C.c_int32), ("pending", C.c_int32), ("pcg_batches", C.c_int64),
-                ("pcg_batched_solves", C.c_int64)]
+                ("pcg_batched_solves", C.c_int64), ("eval_launches", C.c_int64),
+                ("eval_batched_phases", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -116,6 +118,7 @@ SIGNATURES = {
     "ppn_engine_get_state": (C.c_int, [P, C.c_int32, dp, dp]),
     "ppn_engine_get_info": (C.c_int, [P, C.POINTER(ppn_engine_info)]),
     "ppn_engine_set_pcg_batching": (C.c_int, [P, C.c_int32]),
+    "ppn_engine_set_batching": (C.c_int, [P, C.c_int32]),
 }
 
 _lib = None

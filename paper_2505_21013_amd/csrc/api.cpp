@@ -498,7 +498,19 @@ ppn_status ppn_engine_get_state(ppn_engine* e, int32_t scene_id, double* x_out, 
 ppn_status ppn_engine_set_pcg_batching(ppn_engine* e, int32_t enable) {
   ENGINE(e);
   return guarded(nullptr, [&]() -> ppn_status {
-    EG.set_pcg_batching(enable != 0);
+    EG.set_batching(enable != 0 ? PPN_BATCH_PCG : 0);
+    return PPN_OK;
+  });
+}
+
+ppn_status ppn_engine_set_batching(ppn_engine* e, int32_t flags) {
+  ENGINE(e);
+  if (flags < 0 || flags > (PPN_BATCH_PCG | PPN_BATCH_EVAL) || (flags == PPN_BATCH_EVAL)) {
+    g_error = "batching flags: 0, PPN_BATCH_PCG, or PPN_BATCH_PCG | PPN_BATCH_EVAL";
+    return PPN_ERR_ARG;
+  }
+  return guarded(nullptr, [&]() -> ppn_status {
+    EG.set_batching(flags);
     return PPN_OK;
   });
 }

@@ -61,6 +61,8 @@ struct PcgVec {
   double* x = nullptr;        // [N][3] solution
 };
 
+struct EvalJob;
+
 struct Dev {
   int32_t N = 0, T = 0, E = 0;
   int64_t NB = 0;
@@ -71,6 +73,9 @@ struct Dev {
   int32_t n_groups = 0;   // 64-row groups of the sliced-ELL matrix
   int64_t n_slots = 0;    // smax * n_groups (slot-major block rows of the full pattern)
   int64_t n_hslots = 0;   // block rows of the half storage (hsmax * n_groups + 1)
+  int32_t by_distance = 0;  // slots ordered by distance (large matrices), else CSR order
+  int32_t f32_full = 0;     // the mixed form's FP32 copy is in the full layout (CSR-ordered
+                            // matrices), read with col32; else it mirrors the half storage
   int32_t nD = 0;         // Dirichlet vertices
   double h = 1.0 / 30.0;
   double k_dir = 1e8;
@@ -113,7 +118,10 @@ struct Dev {
   double* zd = nullptr;    // [2][N][6]: (z, d) records by PCG iteration parity
   double* rinf = nullptr;  // [N]
   // mixed precision (null in FP64 scenes)
-  float* vals32 = nullptr;  // [n_hslots * 9 * 64]: per half slot four [64] float2 entry pairs
+  float* vals32 = nullptr;  // FP32 matrix: full layout [n_slots * 9 * 64] (f32_full) or the half
+                            // storage's [n_hslots * 9 * 64]; per block row four [64] float2 entry
+                            // pairs (0,1) (2,3) (4,5) (6,7), then entry 8 as [64] float
+  int32_t* col32 = nullptr; // [n_slots * 64] columns of the full-layout FP32 product (f32_full)
                             // (0,1) (2,3) (4,5) (6,7), then entry 8 as [64] float
   float* pinv32 = nullptr;  // [6][N]
   double* e = nullptr;      // [N][3] correction of one refinement round
@@ -130,7 +138,33 @@ struct Dev {
   double* scal = nullptr;   // [16] final reduced values
   PcgState* pcg = nullptr;
   int32_t* flag = nullptr;  // [4] misc device flags (bad element count, ...)
+  EvalJob* job = nullptr;   // [1] this scene's own table for the evaluation kernels
 };
+
+// One scene's share of a shared launch of the evaluation kernels (element
+// quantities, assembly, norm reduction) or of the line-search energy kernel.
+// Every kernel of these phases takes a table of jobs: workgroup b finds the job
+// whose range [wg, wg + count) holds it and runs that scene's code with the
+// local index b - wg.  The ranges start at multiples of 8, so that a scene's
+// workgroups meet the same XCDs as when it runs alone.  A single scene runs the
+// same kernels with a table of one job, so its results are the same bit for
+// bit whether or not it shares a launch.
+struct EvalJob {
+  Dev D;
+  int32_t wg_elem, wg_vert, wg_edge, wg_ls;  // first workgroup in each kernel's grid
+  int32_t n_gamma, pad;
+  double gamma[4];                           // line-search step sizes
+};
+// Workgroups of one scene in each kernel (multiples of 8).
+int eval_wgs_elem(const Dev& D);
+int eval_wgs_vert(const Dev& D);
+int eval_wgs_edge(const Dev& D);
+int eval_wgs_ls(const Dev& D);
+// Sums of the above over a table (host side), and the table offsets set in place.
+struct EvalGrid {
+  int elem = 0, vert = 0, edge = 0, ls = 0;
+};
+EvalGrid layout_eval_jobs(EvalJob* jobs, int n);
 
 // Index of entry e (row-major 3x3) of the sliced-ELL block at position
 // pos = slot * 64 + lane, in 64-bit arithmetic.  Per slot the 64 lanes'
@@ -145,6 +179,10 @@ __host__ __device__ inline size_t value_index(int32_t pos, int e) {
 
 // Bytes of the FP64 matrix values (half storage: 9 entries of 64 rows per half slot).
 inline int64_t matrix_bytes(const Dev& D) { return D.n_hslots * 9 * 64 * int64_t(sizeof(double)); }
+// Bytes of the mixed form's FP32 copy (9 entries of 64 rows per block row).
+inline int64_t matrix_bytes_f32(const Dev& D) {
+  return (D.f32_full ? D.n_slots : D.n_hslots) * 9 * 64 * int64_t(sizeof(float));
+}
 
 // Load modes of the PCG product, chosen per launch from the size of the matrix
 // values (FP64, or the FP32 copy; summed over the jobs of a batched launch).
@@ -172,8 +210,18 @@ inline int load_mode(int64_t bytes) {
 // ---- launchers (all asynchronous on `st`) --------------------------------
 void launch_precompute(const Dev& D, double rho, hipStream_t st);
 void launch_predict(const Dev& D, hipStream_t st);
-void launch_elem_eval(const Dev& D, hipStream_t st);
-void launch_assemble_full(const Dev& D, hipStream_t st);  // vertex + edge kernels, norm partials
+// Evaluation at the current x for the jobs of a table (device memory): the
+// element kernel (which also clears the projected flags), the vertex and edge
+// assembly passes and the reduction of |g|_2^2 and |g|_inf into each scene's
+// scal[0..1].
+void launch_evaluate_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st);
+// Re-assembly only (vertex and edge passes) of the jobs' matrices and gradients.
+void launch_assemble_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st);
+// Psi(x + gamma_k dx) - Psi(x) for each job's n_gamma step sizes into its scal[0..3].
+void launch_energy_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st);
+void launch_elem_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st);
+// k_reduce of every job's partial slots into its scal (one workgroup per job).
+void launch_reduce_jobs(const EvalJob* jobs, int n, int first_slot, int n_sum, int n_max, hipStream_t st);
 void launch_reduce(const Dev& D, int first_slot, int n_sum, int n_max, hipStream_t st);
 // The same over partials written with the PCG grid's stride (Gp).
 void launch_reduce_pcg(const Dev& D, int first_slot, int n_sum, hipStream_t st);
@@ -221,8 +269,9 @@ struct PcgJob {
 void launch_pcg_batch_init(const PcgJob<double>* jobs, int n, int total_wg, hipStream_t st);
 void launch_pcg_batch_init(const PcgJob<float>* jobs, int n, int total_wg, hipStream_t st);
 // any_first: some job starts at this iteration (its first product is a
-// separate instance, launched only then).  matrix_bytes: the jobs' summed
-// FP64 matrix size (selects the load mode; an FP32 copy takes half of it).
+// separate instance, launched only then).  matrix_bytes: the summed size of
+// the matrix values the jobs read (matrix_bytes, or matrix_bytes_f32 for the
+// FP32 copies; selects the load mode).
 void launch_pcg_batch_iter(const PcgJob<double>* jobs, int n, int total_wg, int j, bool any_first,
                            int64_t matrix_bytes, hipStream_t st);
 void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j, bool any_first,
@@ -230,15 +279,16 @@ void launch_pcg_batch_iter(const PcgJob<float>* jobs, int n, int total_wg, int j
 void launch_pcg_batch_gather(const PcgJob<double>* jobs, int n, PcgState* out, hipStream_t st);
 void launch_pcg_batch_gather(const PcgJob<float>* jobs, int n, PcgState* out, hipStream_t st);
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
-// FP32 copy of the matrix values (n_rows block rows of 64), entries paired for 8-byte loads.
-void launch_sell_to_f32(const double* src, float* dst, int64_t n_rows, hipStream_t st);
+// The mixed form's FP32 copy of the matrix: in the full sliced-ELL layout
+// (each slot's block at its own position, lower blocks transposed) when
+// D.f32_full, else entry by entry in the half storage's layout.
+void launch_matrix_to_f32(const Dev& D, hipStream_t st);
 void launch_refine_init(const Dev& D, hipStream_t st);      // dx = 0, r = -g, |r|^2 partials
 void launch_refine_add(const Dev& D, const double* e, hipStream_t st);  // dx += e
 void launch_refine_residual(const Dev& D, hipStream_t st);  // r = -g - H dx, |r|^2 partials
 void launch_dx_stats(const Dev& D, hipStream_t st);  // |dx|_inf, g.dx -> scal[0..1]
 void launch_safety_dir(const Dev& D, hipStream_t st);
 void launch_rinf_from(const Dev& D, const double* g, hipStream_t st);  // rinf_i = max_c |g_(i,c)|
-void launch_energy_diff(const Dev& D, int n_gamma, const double* gam, hipStream_t st);
 void launch_axpy_x(const Dev& D, double gamma, hipStream_t st);
 void launch_finish_step(const Dev& D, hipStream_t st);
 void launch_spmv_plain(const Dev& D, const double* d, double* q, hipStream_t st);

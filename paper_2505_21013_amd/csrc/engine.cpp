@@ -34,14 +34,16 @@ int32_t Engine::n_scenes() {
   return int32_t(slots_.size());
 }
 
-void Engine::set_pcg_batching(bool on) {
+void Engine::set_batching(int flags) {
   std::lock_guard<std::mutex> lk(mu_);
   for (auto& s : slots_)
-    if (s->busy) throw HipError{"set_pcg_batching needs an idle engine", PPN_ERR_STATE};
-  if (!pending_.empty()) throw HipError{"set_pcg_batching needs an idle engine", PPN_ERR_STATE};
+    if (s->busy) throw HipError{"set_batching needs an idle engine", PPN_ERR_STATE};
+  if (!pending_.empty()) throw HipError{"set_batching needs an idle engine", PPN_ERR_STATE};
+  const bool on = (flags & PPN_BATCH_PCG) != 0;
+  batch_eval_ = on && (flags & PPN_BATCH_EVAL) != 0;
   if (on && !batcher_) batcher_ = std::make_unique<PcgBatcher>(device_);
   for (auto& s : slots_)
-    if (s->dev) s->dev->set_batcher(on ? batcher_.get() : nullptr);
+    if (s->dev) s->dev->set_batcher(on ? batcher_.get() : nullptr, batch_eval_);
   if (!on) batcher_.reset();
 }
 
@@ -178,7 +180,7 @@ std::unique_ptr<Scene> Engine::build(Slot& s) {
   sc->load_mesh(std::move(t), s.X.data(), s.tets.data(), nullptr);
   sc->set_material(s.rho, s.E.data(), s.nu.data(), s.E.size() > 1);
   sc->set_state(s.x.data(), s.v.data());
-  sc->set_batcher(batcher_.get());
+  sc->set_batcher(batcher_.get(), batch_eval_);
   return sc;
 }
 
@@ -288,6 +290,8 @@ void Engine::info(ppn_engine_info* out) {
   out->pending = int32_t(pending_.size());
   out->pcg_batches = batcher_ ? batcher_->batches() : 0;
   out->pcg_batched_solves = batcher_ ? batcher_->solves() : 0;
+  out->eval_launches = batcher_ ? batcher_->eval_batcher().launches() : 0;
+  out->eval_batched_phases = batcher_ ? batcher_->eval_batcher().jobs() : 0;
 }
 
 }  // namespace ppn

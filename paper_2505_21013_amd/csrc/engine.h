@@ -43,8 +43,9 @@ class Engine {
   void info(ppn_engine_info* out);
   int32_t n_scenes();
   int64_t footprint(int32_t scene);
-  // Batched PCG solves across scenes on or off; only while no request is pending or running.
-  void set_pcg_batching(bool on);
+  // Shared launches across scenes (PPN_BATCH_* flags: PCG solves, and with them
+  // the evaluation and line-search phases); only while no request is pending or running.
+  void set_batching(int flags);
 
  private:
   using Clock = std::chrono::steady_clock;
@@ -87,6 +88,7 @@ class Engine {
 
   int device_;
   std::unique_ptr<PcgBatcher> batcher_;  // declared before the slots: outlives their scenes
+  bool batch_eval_ = false;
   int64_t budget_;
   int64_t resident_bytes_ = 0;
   int64_t admissions_ = 0, evictions_ = 0;

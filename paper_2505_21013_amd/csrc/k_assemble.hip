@@ -75,11 +75,11 @@ __device__ inline void gather_edge(const Dev& D, int k) {
 // in LDS and one thread per vertex finishes it.
 constexpr int kVChunk = kBlock / 9;  // 28 vertices (252 threads) per chunk
 
-__global__ __launch_bounds__(kBlock) void k_assemble_vertex(Dev D) {
+__device__ __forceinline__ void assemble_vertex_body(const Dev& D, int b) {
   __shared__ double lds[16];
   __shared__ double sv[kVChunk][9];
   const int G = D.G;
-  const int w = logical_wg(G);
+  const int w = xcd_chunk(b, G);
   const int i0 = w * D.rows_per_wg, i1 = min(D.N, i0 + D.rows_per_wg);
   const double ih2 = 1.0 / (D.h * D.h);
   const int t = threadIdx.x, vl = t / 9, c = t % 9;
@@ -137,9 +137,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble_vertex(Dev D) {
 // while they are in that XCD's L2.
 constexpr int kEBlock = 1024;
 constexpr int kEChunk = kEBlock / 9;  // 113 edges (1017 threads) per workgroup
-__global__ __launch_bounds__(kEBlock) void k_assemble_edge(Dev D, int n_wg) {
+// Edge-pass workgroups of a scene: a multiple of 8 (the extra ones exit at once).
+__host__ __device__ inline int eval_wgs_edge_dev(const Dev& D) {
+  return D.E > 0 ? int(((int64_t(D.E) + kEChunk - 1) / kEChunk + 7) / 8 * 8) : 0;
+}
+__device__ __forceinline__ void assemble_edge_body(const Dev& D, int b, int n_wg) {
   const int vl = threadIdx.x / 9, c = threadIdx.x % 9;
-  const int64_t k = int64_t(logical_wg(n_wg)) * kEChunk + vl;
+  const int64_t k = int64_t(xcd_chunk(b, n_wg)) * kEChunk + vl;
   if (vl >= kEChunk || k >= D.E) return;
   double s = 0.0;
 #pragma unroll 4
@@ -147,13 +151,16 @@ __global__ __launch_bounds__(kEBlock) void k_assemble_edge(Dev D, int n_wg) {
   D.vals[value_index(D.eblk_up[k], c)] = s;
 }
 
-void launch_assemble_full(const Dev& D, hipStream_t st) {
-  k_assemble_vertex<<<D.G, kBlock, 0, st>>>(D);
-  if (D.E > 0) {
-    // logical_wg needs a multiple of 8 workgroups; the extra ones exit at once.
-    const int n_wg = int(((int64_t(D.E) + kEChunk - 1) / kEChunk + 7) / 8 * 8);
-    k_assemble_edge<<<n_wg, kEBlock, 0, st>>>(D, n_wg);
-  }
+__global__ __launch_bounds__(kBlock) void k_assemble_vertex(const EvalJob* __restrict__ jobs, int n) {
+  int w;
+  const EvalJob& J = eval_job<1>(jobs, n, w);
+  assemble_vertex_body(J.D, w);
+}
+
+__global__ __launch_bounds__(kEBlock) void k_assemble_edge(const EvalJob* __restrict__ jobs, int n) {
+  int w;
+  const EvalJob& J = eval_job<2>(jobs, n, w);
+  assemble_edge_body(J.D, w, eval_wgs_edge_dev(J.D));
 }
 
 // Re-gather the 10 blocks of each listed (just projected) element.  Blocks
@@ -292,6 +299,65 @@ __global__ __launch_bounds__(kBlock) void k_reduce(Dev D, int first, int n_sum, 
 
 void launch_reduce(const Dev& D, int first_slot, int n_sum, int n_max, hipStream_t st) {
   k_reduce<<<1, kBlock, 0, st>>>(D, first_slot, n_sum, n_max, D.G);
+}
+
+// k_reduce for every job of a table: workgroup k reduces job k's partials
+// (written with its G workgroups) into its scal.
+__global__ __launch_bounds__(kBlock) void k_reduce_jobs(const EvalJob* __restrict__ jobs, int first,
+                                                        int n_sum, int n_max) {
+  __shared__ double lds[16];
+  const Dev& D = jobs[blockIdx.x].D;
+  const int G = D.G;
+  for (int k = 0; k < n_sum + n_max; ++k) {
+    const double* p = D.part + size_t(first + k) * G;
+    double v;
+    if (k < n_sum) {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < G; i += kBlock) s += p[i];
+      v = block_sum(s, lds);
+    } else {
+      double s = 0.0;
+      for (int i = threadIdx.x; i < G; i += kBlock) s = fmax(s, p[i]);
+      v = block_max(s, lds);
+    }
+    if (threadIdx.x == 0) D.scal[k] = v;
+  }
+}
+
+void launch_reduce_jobs(const EvalJob* jobs, int n, int first_slot, int n_sum, int n_max, hipStream_t st) {
+  if (n > 0) k_reduce_jobs<<<n, kBlock, 0, st>>>(jobs, first_slot, n_sum, n_max);
+}
+
+int eval_wgs_vert(const Dev& D) { return D.G; }
+int eval_wgs_edge(const Dev& D) { return eval_wgs_edge_dev(D); }
+
+EvalGrid layout_eval_jobs(EvalJob* jobs, int n) {
+  EvalGrid g;
+  for (int k = 0; k < n; ++k) {
+    EvalJob& j = jobs[k];
+    j.wg_elem = g.elem;
+    j.wg_vert = g.vert;
+    j.wg_edge = g.edge;
+    j.wg_ls = g.ls;
+    g.elem += eval_wgs_elem(j.D);
+    g.vert += eval_wgs_vert(j.D);
+    g.edge += eval_wgs_edge(j.D);
+    g.ls += eval_wgs_ls(j.D);
+  }
+  return g;
+}
+
+void launch_assemble_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st) {
+  if (n <= 0) return;
+  k_assemble_vertex<<<gr.vert, kBlock, 0, st>>>(jobs, n);
+  if (gr.edge > 0) k_assemble_edge<<<gr.edge, kEBlock, 0, st>>>(jobs, n);
+}
+
+void launch_evaluate_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st) {
+  if (n <= 0) return;
+  launch_elem_jobs(jobs, n, gr, st);
+  launch_assemble_jobs(jobs, n, gr, st);
+  launch_reduce_jobs(jobs, n, kPartG2, 1, 1, st);
 }
 
 void launch_reduce_pcg(const Dev& D, int first_slot, int n_sum, hipStream_t st) {

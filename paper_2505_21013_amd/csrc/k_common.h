@@ -84,9 +84,27 @@ constexpr int kSym3[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 // Workgroups are dispatched round-robin over the 8 XCDs.  Map the hardware
 // index so that XCD x owns the contiguous logical chunks [x*G/8, (x+1)*G/8):
 // neighbouring rows then share an L2.  Requires G % 8 == 0.
-__device__ inline int logical_wg(int G) {
+__device__ inline int xcd_chunk(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
+__device__ inline int logical_wg(int G) { return xcd_chunk(blockIdx.x, G); }
+
+// The job of a shared launch that owns this workgroup (largest range start <=
+// blockIdx.x, by binary search over the table) and the workgroup's index
+// within that job's range.  kField picks the kernel's range: 0 element, 1
+// vertex, 2 edge, 3 line search.
+template <int kField>
+__device__ inline int eval_range_start(const EvalJob& j) {
+  return kField == 0 ? j.wg_elem : kField == 1 ? j.wg_vert : kField == 2 ? j.wg_edge : j.wg_ls;
+}
+template <int kField>
+__device__ inline const EvalJob& eval_job(const EvalJob* __restrict__ jobs, int n, int& w) {
   const int b = blockIdx.x;
-  return (b & 7) * (G >> 3) + (b >> 3);
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (eval_range_start<kField>(jobs[mid]) <= b) lo = mid; else hi = mid - 1;
+  }
+  w = b - eval_range_start<kField>(jobs[lo]);
+  return jobs[lo];
 }
 
 }  // namespace ppn

@@ -121,10 +121,13 @@ void launch_precompute(const Dev& D, double rho, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- element evaluation
-__global__ __launch_bounds__(kBlock) void k_elem_eval(Dev D) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
+// Element e = w * kBlock + thread of a scene (w: the workgroup's index in the
+// scene's range); also clears the element's projected flag for the iteration.
+__device__ __forceinline__ void elem_eval_body(const Dev& D, int w) {
+  const int e = w * kBlock + threadIdx.x;
   if (e >= D.T) return;
   const int T = D.T;
+  D.proj[e] = 0;
   int v[4];
   double xs[4][3];
   load_corners(D, D.x, e, v, xs);
@@ -204,9 +207,14 @@ __global__ __launch_bounds__(kBlock) void k_elem_eval(Dev D) {
   }
 }
 
-void launch_elem_eval(const Dev& D, hipStream_t st) {
-  k_elem_eval<<<(D.T + kBlock - 1) / kBlock, kBlock, 0, st>>>(D);
+__global__ __launch_bounds__(kBlock) void k_elem_eval(const EvalJob* __restrict__ jobs, int n) {
+  int w;
+  const EvalJob& J = eval_job<0>(jobs, n, w);
+  elem_eval_body(J.D, w);
 }
+
+int eval_wgs_elem(const Dev& D) { return ((D.T + kBlock - 1) / kBlock + 7) / 8 * 8; }
+int eval_wgs_ls(const Dev& D) { return D.G; }
 
 // ---------------------------------------------------------------- time integration helpers
 __global__ __launch_bounds__(kBlock) void k_predict(Dev D) {
@@ -248,14 +256,14 @@ void launch_finish_step(const Dev& D, hipStream_t st) {
 // ---------------------------------------------------------------- line-search energy difference
 // Psi(x + gamma_k dx) - Psi(x), summed per term: per element V (psi(F_k) - psi(F_0)),
 // per vertex m/(2h^2) s.(2(x - xhat) + s) and the penalty analogue, s = gamma_k dx.
-struct Gammas {
-  double g[4];
-};
-
-__global__ __launch_bounds__(kBlock) void k_energy_diff(Dev D, int ng, Gammas gm) {
+// Workgroup wg of the scene's G: a contiguous share of its elements and vertices.
+__device__ __forceinline__ void energy_diff_body(const Dev& D, int ng, const double* __restrict__ gam,
+                                                 int wg) {
   __shared__ double lds[16];
   const int G = D.G;
-  const int wg = blockIdx.x;
+  double g4[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g4[k] = k < ng ? gam[k] : 0.0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const int epw = (D.T + G - 1) / G;
   const int e0 = wg * epw, e1 = min(D.T, e0 + epw);
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_diff(Dev D, int ng, Gammas gm
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int i = 0; i < 3; ++i) xk[a][i] = xs[a][i] + gm.g[k] * ds[a][i];
+          for (int i = 0; i < 3; ++i) xk[a][i] = xs[a][i] + g4[k] * ds[a][i];
         def_grad(xk, b, F);
         acc[k] += V * (snh_psi(F, mu, lam) - p0);
       }
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_diff(Dev D, int ng, Gammas gm
         double t = 0.0, p = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double s = gm.g[k] * D.dx[3 * i + c];
+          const double s = g4[k] * D.dx[3 * i + c];
           const double xi = D.x[3 * i + c];
           t += s * (2.0 * (xi - D.xhat[3 * i + c]) + s);
           if (di >= 0) p += s * (2.0 * (xi - D.xbar[3 * di + c]) + s);
@@ -314,11 +322,21 @@ __global__ __launch_bounds__(kBlock) void k_energy_diff(Dev D, int ng, Gammas gm
   }
 }
 
-void launch_energy_diff(const Dev& D, int n_gamma, const double* gam, hipStream_t st) {
-  Gammas gm;
-  for (int k = 0; k < 4; ++k) gm.g[k] = k < n_gamma ? gam[k] : 0.0;
-  k_energy_diff<<<D.G, kBlock, 0, st>>>(D, n_gamma, gm);
-  launch_reduce(D, kPartA, 4, 0, st);
+__global__ __launch_bounds__(kBlock) void k_energy_diff(const EvalJob* __restrict__ jobs, int n) {
+  int w;
+  const EvalJob& J = eval_job<3>(jobs, n, w);
+  energy_diff_body(J.D, J.n_gamma, J.gamma, w);
+}
+
+void launch_energy_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st) {
+  if (n <= 0) return;
+  k_energy_diff<<<gr.ls, kBlock, 0, st>>>(jobs, n);
+  launch_reduce_jobs(jobs, n, kPartA, 4, 0, st);
+}
+
+void launch_elem_jobs(const EvalJob* jobs, int n, const EvalGrid& gr, hipStream_t st) {
+  if (n <= 0) return;
+  k_elem_eval<<<gr.elem, kBlock, 0, st>>>(jobs, n);
 }
 
 }  // namespace ppn

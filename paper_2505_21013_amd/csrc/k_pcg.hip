@@ -228,6 +228,31 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
   // Two slots in flight per lane, and each slot's column and value reference
   // loaded one slot ahead: the value loads depend on the reference (measured on
   // the 1.57M-tet cube: 55.5 us per FP64 product against 61.0 with neither).
+  if (sizeof(M) == 4 && D.f32_full) {
+    // full-layout FP32 copy: the block of slot s sits at its own position
+#pragma unroll 2
+    for (int s = 0; s < S; ++s) {
+      const int slot = s * D.n_groups + g;
+      const int c = D.col32[slot * kSell + l];
+      const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
+      const double2 a = p[0], b = p[1];
+      const M z0 = M(a.x), z1 = M(a.y), z2 = M(b.x);
+      M w[9];
+      load_block<kLoad>(vals, slot * kSell + l, w);
+      qz[0] += block_row(w[0], w[1], w[2], z0, z1, z2);
+      qz[1] += block_row(w[3], w[4], w[5], z0, z1, z2);
+      qz[2] += block_row(w[6], w[7], w[8], z0, z1, z2);
+      if (with_d) {
+        const double2 e = p[2];
+        const M d0 = M(b.y), d1 = M(e.x), d2 = M(e.y);
+        qd[0] += block_row(w[0], w[1], w[2], d0, d1, d2);
+        qd[1] += block_row(w[3], w[4], w[5], d0, d1, d2);
+        qd[2] += block_row(w[6], w[7], w[8], d0, d1, d2);
+      }
+    }
+    return;
+  }
+  // half storage (FP64, or its FP32 copy)
   int2 nxt = S > 0 ? slot_colref(D, g, l) : make_int2(0, 0);
 #pragma unroll 2
   for (int s = 0; s < S; ++s) {
@@ -454,16 +479,17 @@ static void pcg_iter_k(const Dev& D, const PcgVec<T>& V, int j, double tol2, int
   k_pcg_update<T, kLoad == kLoadStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
 }
 
-// fp64_bytes: the FP64 matrix size; the FP32 copy of the mixed form takes half.
+// The matrix values a product of type T reads: the FP64 half storage, or the
+// mixed form's full-layout FP32 copy.
 template <typename T>
-static int load_mode_of(int64_t fp64_bytes) {
-  return load_mode(sizeof(T) == 8 ? fp64_bytes : fp64_bytes / 2);
+static int load_mode_of(const Dev& D) {
+  return load_mode(sizeof(T) == 8 ? matrix_bytes(D) : matrix_bytes_f32(D));
 }
 
 template <typename T>
 static void pcg_iter(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                      hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
-  switch (D.pcg_load >= 0 ? D.pcg_load : load_mode_of<T>(matrix_bytes(D))) {
+  switch (D.pcg_load >= 0 ? D.pcg_load : load_mode_of<T>(D)) {
     case kLoadStream: pcg_iter_k<T, kLoadStream>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop); break;
     case kLoadCached: pcg_iter_k<T, kLoadCached>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop); break;
     default: pcg_iter_k<T, kLoadSmall>(D, V, j, tol2, maxit, st, ev_spmv_start, ev_spmv_stop);
@@ -516,31 +542,42 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ sr
     dst[k] = float(__builtin_nontemporal_load(src + k));
 }
 
-// FP32 copy of the matrix values (n_rows block rows of 64) in the paired layout
-// read by load_block.
-__global__ __launch_bounds__(kBlock) void k_sell_to_f32(const double* __restrict__ src,
-                                                        float* __restrict__ dst, int64_t n_rows) {
+// FP32 copy of the matrix in the full sliced-ELL layout (every slot's block at
+// its own position slot * 64 + lane, lower blocks transposed here once per
+// solve), entries paired as read by load_block: the FP32 product of a small
+// (CSR-ordered) matrix then reads contiguous runs and 4-byte columns, without
+// references (measured: 30.9 against 30.1 mixed steps/s on the 122,880-tet
+// beam, 307 against 286 on the 64-scene batch).  Large, distance-ordered
+// matrices keep an FP32 copy of the half storage (36.5 against 39.1 us per
+// product on the 1.57M-tet cube).
+__global__ __launch_bounds__(kBlock) void k_half_to_full_f32(Dev D, const double* __restrict__ src,
+                                                             float* __restrict__ dst) {
   const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n_rows * kSell; k += stride) {
+  const int64_t n = D.n_slots * kSell;
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += stride) {
+    const int32_t ref = reinterpret_cast<const int2*>(D.colref)[k].y;
+    double w[9];
+    load_block<kLoadStream>(src, ref & kRefPosMask, w);
+    orient_block(ref, w);
     const int64_t slot = k / kSell;
     const int l = int(k % kSell);
-    const double* v = src + slot * (9 * kSell);
-    const f64x2* v2 = reinterpret_cast<const f64x2*>(v) + l;
     float* o = dst + slot * (9 * kSell);
     float2* o2 = reinterpret_cast<float2*>(o) + l;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const f64x2 e = __builtin_nontemporal_load(v2 + p * kSell);
-      o2[p * kSell] = make_float2(float(e.x), float(e.y));
-    }
-    o[8 * kSell + l] = float(__builtin_nontemporal_load(v + 8 * kSell + l));
+    for (int p = 0; p < 4; ++p) o2[p * kSell] = make_float2(float(w[2 * p]), float(w[2 * p + 1]));
+    o[8 * kSell + l] = float(w[8]);
   }
 }
 
-void launch_sell_to_f32(const double* src, float* dst, int64_t n_rows, hipStream_t st) {
-  if (n_rows <= 0) return;
-  const int64_t blocks = std::min<int64_t>((n_rows * kSell + kBlock - 1) / kBlock, 8192);
-  k_sell_to_f32<<<unsigned(blocks), kBlock, 0, st>>>(src, dst, n_rows);
+void launch_matrix_to_f32(const Dev& D, hipStream_t st) {
+  if (!D.f32_full) {
+    launch_to_f32(D.vals, D.vals32, D.n_hslots * 9 * kSell, st);
+    return;
+  }
+  const int64_t n = D.n_slots * kSell;
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+  k_half_to_full_f32<<<unsigned(blocks), kBlock, 0, st>>>(D, D.vals, D.vals32);
 }
 
 void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
@@ -669,11 +706,11 @@ static void batch_iter_k(const PcgJob<M>* jobs, int n, int total_wg, int j, bool
   k_pcg_spmv_batch<M, false, kLoad><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
   k_pcg_update_batch<M, kLoad == kLoadStream><<<total_wg, kPcgBlock, 0, st>>>(jobs, n, j);
 }
-// matrix_bytes: the summed matrix size of the jobs (they share the cache).
+// matrix_bytes: the summed size of the matrix values the jobs read (they share the cache).
 template <typename M>
 static void batch_iter(const PcgJob<M>* jobs, int n, int total_wg, int j, bool any_first,
                        int64_t matrix_bytes, hipStream_t st) {
-  switch (load_mode_of<M>(matrix_bytes)) {
+  switch (load_mode(matrix_bytes)) {
     case kLoadStream: batch_iter_k<M, kLoadStream>(jobs, n, total_wg, j, any_first, st); break;
     case kLoadCached: batch_iter_k<M, kLoadCached>(jobs, n, total_wg, j, any_first, st); break;
     default: batch_iter_k<M, kLoadSmall>(jobs, n, total_wg, j, any_first, st);

@@ -15,7 +15,101 @@ namespace ppn {
                      e_ == hipErrorOutOfMemory ? PPN_ERR_OOM : PPN_ERR_DEVICE};                \
   } while (0)
 
-PcgBatcher::PcgBatcher(int device) : device_(device) {
+EvalBatcher::EvalBatcher(int device) : device_(device) {
+  BCHK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+  BCHK(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+  th_ = std::thread([this] { loop(); });
+}
+
+EvalBatcher::~EvalBatcher() {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  th_.join();
+  (void)hipStreamSynchronize(st_);
+  if (d_tab_) (void)hipFree(d_tab_);
+  if (h_tab_) (void)hipHostFree(h_tab_);
+  (void)hipEventDestroy(ev_);
+  (void)hipStreamDestroy(st_);
+}
+
+void EvalBatcher::run(const EvalJob& job, int kind) {
+  Req r;
+  r.job = job;
+  r.kind = kind;
+  std::unique_lock<std::mutex> lk(mu_);
+  q_.push_back(&r);
+  cv_.notify_one();
+  cv_done_.wait(lk, [&] { return r.done; });
+  if (!r.err.empty()) throw HipError{r.err, PPN_ERR_DEVICE};
+}
+
+// One launch of each kernel of the phase for every request in reqs; the
+// requests' own step sizes (line search) travel in their table entries.
+void EvalBatcher::launch(std::vector<Req*>& reqs, int kind) {
+  const size_t n = reqs.size();
+  if (n > cap_) {
+    BCHK(hipStreamSynchronize(st_));
+    if (d_tab_) (void)hipFree(d_tab_);
+    if (h_tab_) (void)hipHostFree(h_tab_);
+    d_tab_ = nullptr;
+    h_tab_ = nullptr;
+    cap_ = std::max<size_t>(2 * cap_, std::max<size_t>(n, 64));
+    BCHK(hipMalloc(reinterpret_cast<void**>(&d_tab_), cap_ * sizeof(EvalJob)));
+    BCHK(hipHostMalloc(reinterpret_cast<void**>(&h_tab_), cap_ * sizeof(EvalJob)));
+  }
+  for (size_t k = 0; k < n; ++k) h_tab_[k] = reqs[k]->job;
+  const EvalGrid gr = layout_eval_jobs(h_tab_, int(n));
+  BCHK(hipMemcpyAsync(d_tab_, h_tab_, n * sizeof(EvalJob), hipMemcpyHostToDevice, st_));
+  if (kind == 0)
+    launch_evaluate_jobs(d_tab_, int(n), gr, st_);
+  else
+    launch_energy_jobs(d_tab_, int(n), gr, st_);
+  BCHK(hipGetLastError());
+  BCHK(hipEventRecord(ev_, st_));
+  BCHK(hipEventSynchronize(ev_));  // also keeps h_tab_ until its copy is done
+}
+
+void EvalBatcher::loop() {
+  (void)hipSetDevice(device_);
+  std::unique_lock<std::mutex> lk(mu_);
+  std::vector<Req*> by_kind[2];
+  for (;;) {
+    cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+    if (stop_ && q_.empty()) return;
+    while (!q_.empty()) {
+      Req* r = q_.front();
+      q_.pop_front();
+      by_kind[r->kind].push_back(r);
+    }
+    lk.unlock();
+    std::string err;
+    int64_t nl = 0, nj = 0;
+    for (int kind = 0; kind < 2; ++kind) {
+      if (by_kind[kind].empty()) continue;
+      try {
+        launch(by_kind[kind], kind);
+        nl++;
+        nj += int64_t(by_kind[kind].size());
+      } catch (const HipError& e) {
+        err = e.msg;
+        for (Req* r : by_kind[kind]) r->err = err;
+      }
+    }
+    lk.lock();
+    launches_ += nl;
+    jobs_ += nj;
+    for (auto& v : by_kind) {
+      for (Req* r : v) r->done = true;
+      v.clear();
+    }
+    cv_done_.notify_all();
+  }
+}
+
+PcgBatcher::PcgBatcher(int device) : device_(device), eval_(device) {
   BCHK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
   lanes_[1].fp32 = true;
   for (Lane& L : lanes_)
@@ -231,7 +325,7 @@ bool PcgBatcher::step(Lane& L, std::vector<Job*>& joining, std::vector<Job*>& fi
     const Job& j = *L.members[size_t(k)];
     tab[k] = entry<M>(j.D, vec_of<M>(j.V64, j.V32), j.src, j.sign, j.tol2, j.maxit, total, j.j0);
     total += j.D.Gp;
-    mbytes += matrix_bytes(j.D);
+    mbytes += sizeof(M) == 8 ? matrix_bytes(j.D) : matrix_bytes_f32(j.D);
     L.polled[p].push_back(j.id);
   }
   const auto* dtab = static_cast<const PcgJob<M>*>(L.d_tab[p]);

@@ -26,10 +26,50 @@
 
 namespace ppn {
 
+// Shared launches of the per-iteration evaluation kernels (element quantities,
+// assembly, gradient norms) and of the line-search energy kernel: scenes that
+// reach one of these phases hand it over (their stream drained) and wait; a
+// thread with its own stream takes every request present, lays the scenes out
+// in one job table and runs each kernel of the phase once for all of them.
+class EvalBatcher {
+ public:
+  explicit EvalBatcher(int device);
+  ~EvalBatcher();
+  void run(const EvalJob& job, int kind);  // kind 0: evaluation, 1: line search; blocks
+  int64_t launches() const { return launches_; }  // shared phase launches
+  int64_t jobs() const { return jobs_; }          // scene phases carried by them
+
+ private:
+  struct Req {
+    EvalJob job;
+    int kind = 0;
+    bool done = false;
+    std::string err;
+  };
+  void loop();
+  void launch(std::vector<Req*>& reqs, int kind);
+  int device_;
+  hipStream_t st_ = nullptr;
+  hipEvent_t ev_ = nullptr;
+  EvalJob* d_tab_ = nullptr;
+  EvalJob* h_tab_ = nullptr;
+  size_t cap_ = 0;
+  int64_t launches_ = 0, jobs_ = 0;
+  std::mutex mu_;
+  std::condition_variable cv_, cv_done_;
+  std::deque<Req*> q_;
+  bool stop_ = false;
+  std::thread th_;
+};
+
 class PcgBatcher {
  public:
   explicit PcgBatcher(int device);
   ~PcgBatcher();
+  // The evaluation and line-search phases of the scenes that share this batcher.
+  void evaluate(const EvalJob& j) { eval_.run(j, 0); }
+  void energy(const EvalJob& j) { eval_.run(j, 1); }
+  const EvalBatcher& eval_batcher() const { return eval_; }
   // Solve on the batcher's stream; blocks until done.  The caller's stream
   // must have completed the work the solve reads.
   void solve(const Dev& D, const PcgVec<double>& V, const double* src, double sign, double rtol,
@@ -90,6 +130,7 @@ class PcgBatcher {
   void free_lane(Lane& L);
 
   int device_;
+  EvalBatcher eval_;
   hipStream_t st_ = nullptr;
   Lane lanes_[2];  // FP64 matrix, FP32 matrix
   int64_t batches_ = 0, solves_ = 0;

@@ -76,6 +76,7 @@ void params_defaults(ppn_params* p) {
   p->ls_maxit = 30;
   p->k_dirichlet = 1e8;
   p->pcg_load_mode = -1;
+  p->use_graphs = 1;
 }
 
 Scene::Scene(hipStream_t stream, bool own, int precision)
@@ -115,6 +116,9 @@ T* Scene::alloc(size_t n) {
 }
 
 void Scene::free_all() {
+  if (eval_graph_) (void)hipGraphExecDestroy(eval_graph_);
+  eval_graph_ = nullptr;
+  job_valid_ = false;
   for (void* p : allocs_) (void)hipFree(p);
   allocs_.clear();
   dev_bytes_ = 0;
@@ -146,6 +150,8 @@ static void geometry(Dev& D, const Topology& t) {
   D.n_groups = t.n_groups;
   D.n_slots = t.n_slots;
   D.n_hslots = t.n_hslots;
+  D.by_distance = t.by_distance ? 1 : 0;
+  D.f32_full = t.by_distance ? 0 : 1;
   D.Gp = ((D.n_groups + 3) / 4 + 7) / 8 * 8;
 }
 
@@ -185,7 +191,8 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
   D.zd = alloc.template get<double>(12 * n);
   D.rinf = alloc.template get<double>(n);
   if (precision == PPN_MIXED) {
-    D.vals32 = alloc.template get<float>(size_t(D.n_hslots) * 9 * kSell);
+    D.vals32 = alloc.template get<float>(size_t(D.f32_full ? D.n_slots : D.n_hslots) * 9 * kSell);
+    if (D.f32_full) D.col32 = alloc.template get<int32_t>(size_t(D.n_slots) * kSell);
     D.pinv32 = alloc.template get<float>(6 * n);
     D.e = alloc.template get<double>(3 * n);
     D.ri = alloc.template get<double>(3 * n);
@@ -198,6 +205,7 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
   D.part = alloc.template get<double>(size_t(kPartCount) * std::max(D.G, D.Gp));
   D.scal = alloc.template get<double>(16);
   D.pcg = alloc.template get<PcgState>(1);
+  D.job = alloc.template get<EvalJob>(1);
   D.flag = alloc.template get<int32_t>(4);
 }
 
@@ -253,6 +261,12 @@ void Scene::load_mesh(Topology&& t, const double* rest, const int32_t* tets, con
     DeviceAlloc da{this};
     plan_buffers(D_, precision_, da);
     if (dev_bytes_ != footprint(topo_, precision_)) fail("internal: footprint mismatch", PPN_ERR_DEVICE);
+    {
+      EvalJob e;
+      std::memset(static_cast<void*>(&e), 0, sizeof(e));
+      e.D = D_;
+      grid_ = layout_eval_jobs(&e, 1);
+    }
 
     std::vector<int32_t> soa(4 * m);
     for (size_t e = 0; e < m; ++e)
@@ -277,6 +291,7 @@ void Scene::load_mesh(Topology&& t, const double* rest, const int32_t* tets, con
       colref[2 * k + 1] = topo_.sell_ref[k];
     }
     up(D_.colref, colref.data(), colref.size() * 4);
+    if (D_.col32) up(D_.col32, topo_.sell_col.data(), size_t(D_.n_slots) * kSell * 4);
     up(D_.diag_blk, topo_.diag_pos.data(), n * 4);
     up(D_.eblk_up, topo_.edge_pos.data(), size_t(D_.E) * 4);
     // padding blocks and the zero row of the half storage stay zero for the life of the scene
@@ -389,17 +404,72 @@ void Scene::set_params(const ppn_params& p) {
   if (!(p.k_dirichlet >= 0.0)) fail("k_dirichlet must be >= 0");
   if (p.eig_mirror != 0 && p.eig_mirror != 1) fail("eig_mirror must be 0 or 1");
   if (p.pcg_load_mode < -1 || p.pcg_load_mode > 2) fail("pcg_load_mode must be -1, 0, 1 or 2");
+  if (p.use_graphs != 0 && p.use_graphs != 1) fail("use_graphs must be 0 or 1");
   prm_ = p;
   D_.k_dir = p.k_dirichlet;
   D_.pcg_load = p.pcg_load_mode;
 }
 
 // ---------------------------------------------------------------- building blocks
+// The scene's one-entry table of the evaluation kernels holds a copy of D_
+// (and the line search's step sizes); it is rewritten when that changes.
+void Scene::upload_job(int n_gamma, const double* gam) {
+  EvalJob e;
+  std::memset(static_cast<void*>(&e), 0, sizeof(e));
+  e.D = D_;
+  e.n_gamma = n_gamma;
+  for (int k = 0; k < 4; ++k) e.gamma[k] = k < n_gamma ? gam[k] : 0.0;
+  layout_eval_jobs(&e, 1);
+  if (job_valid_ && std::memcmp(&e, &job_host_, sizeof(e)) == 0) return;
+  job_host_ = e;
+  job_valid_ = true;
+  // from pageable memory: the copy is staged before the call returns
+  HIPCHK(hipMemcpyAsync(D_.job, &job_host_, sizeof(e), hipMemcpyHostToDevice, st_));
+}
+
+// Psi(x + gamma_k dx) - Psi(x) for up to four step sizes into scal[0..n).
+void Scene::energy_diff(int n, const double* gam) {
+  upload_job(n, gam);
+  if (batcher_ && batch_eval_) {
+    sync();
+    batcher_->energy(job_host_);
+  } else {
+    launch_energy_jobs(D_.job, 1, grid_, st_);
+  }
+  LAUNCHCHK();
+}
+
+void Scene::launch_assemble() {
+  upload_job();
+  launch_assemble_jobs(D_.job, 1, grid_, st_);
+}
+
+// Element quantities, assembly and the gradient norms into scal[0..1].  Alone,
+// the launches run as one HIP graph captured at the first call (kernel
+// arguments are the scene's fixed table and grid sizes; what changes lives in
+// the table); handed to the batcher, they share launches with other scenes.
 void Scene::evaluate_at_current_x() {
-  launch_fill_u8(D_.proj, 0, D_.T, st_);
-  launch_elem_eval(D_, st_);
-  launch_assemble_full(D_, st_);
-  launch_reduce(D_, kPartG2, 1, 1, st_);
+  upload_job();
+  if (batcher_ && batch_eval_) {
+    sync();  // the batcher's stream reads what this stream wrote
+    batcher_->evaluate(job_host_);
+  } else if (prm_.use_graphs) {
+    if (!eval_graph_) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+      launch_evaluate_jobs(D_.job, 1, grid_, st_);
+      const hipError_t e = hipStreamEndCapture(st_, &g);
+      if (e == hipSuccess) {
+        const hipError_t ei = hipGraphInstantiate(&eval_graph_, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(ei);
+      }
+      HIPCHK(e);
+    }
+    HIPCHK(hipGraphLaunch(eval_graph_, st_));
+  } else {
+    launch_evaluate_jobs(D_.job, 1, grid_, st_);
+  }
   LAUNCHCHK();
   n_projected_ = 0;
   all_projected_ = false;
@@ -425,7 +495,7 @@ void Scene::project_all() {
   hipEvent_t stop = ev_[3];
   HIPCHK(hipEventRecord(stop, st_));
   launch_fill_u8(D_.proj, 1, D_.T, st_);
-  launch_assemble_full(D_, st_);
+  launch_assemble();
   LAUNCHCHK();
   HIPCHK(hipEventSynchronize(stop));
   float ms = 0.f;
@@ -449,7 +519,7 @@ int32_t Scene::select_and_project(double delta, bool fallback) {
   hipEvent_t stop = ev_[3];
   HIPCHK(hipEventRecord(stop, st_));
   if (int64_t(n) * 8 > D_.T)
-    launch_assemble_full(D_, st_);
+    launch_assemble();
   else
     launch_regather_list(D_, n, st_);
   LAUNCHCHK();
@@ -569,7 +639,7 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
 void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
   constexpr int kMaxRounds = 8;
   constexpr double kMinInner = 1e-6;
-  launch_sell_to_f32(D_.vals, D_.vals32, D_.n_hslots, st_);
+  launch_matrix_to_f32(D_, st_);
   launch_to_f32(D_.pinv, D_.pinv32, int64_t(6) * D_.N, st_);
   launch_refine_init(D_, st_);
   launch_reduce_pcg(D_, kPartA, 1, st_);
@@ -744,8 +814,7 @@ ppn_status Scene::newton_step(int mode, ppn_step_stats* out) {
       const int nb = std::min(4, prm_.ls_maxit + 1 - trial);
       double gam[4];
       for (int q = 0; q < nb; ++q) gam[q] = std::ldexp(1.0, -(trial + q));
-      launch_energy_diff(D_, nb, gam, st_);
-      LAUNCHCHK();
+      energy_diff(nb, gam);
       read_scal(nb, hscal_);
       int q = 0;
       for (; q < nb; ++q)
@@ -955,8 +1024,7 @@ void Scene::energy_difference(const double* x, const double* dx, int32_t n, cons
   HIPCHK(hipMemcpyAsync(D_.dx, dx, size_t(D_.N) * 24, hipMemcpyHostToDevice, st_));
   for (int32_t k = 0; k < n; k += 4) {
     const int nb = std::min(4, n - k);
-    launch_energy_diff(D_, nb, gam + k, st_);
-    LAUNCHCHK();
+    energy_diff(nb, gam + k);
     read_scal(nb, hscal_);
     for (int q = 0; q < nb; ++q) out[k + q] = hscal_[q];
   }

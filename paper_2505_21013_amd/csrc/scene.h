@@ -66,8 +66,12 @@ class Scene {
   void get_state(double* x, double* v);
   void set_state(const double* x, const double* v);
 
-  // Hand PCG solves to a batcher shared with other scenes (nullptr: solve alone).
-  void set_batcher(PcgBatcher* b) { batcher_ = b; }
+  // Hand PCG solves (and, with eval, the evaluation and line-search launches)
+  // to a batcher shared with other scenes (nullptr: everything alone).
+  void set_batcher(PcgBatcher* b, bool eval = false) {
+    batcher_ = b;
+    batch_eval_ = b && eval;
+  }
   bool loaded() const { return D_.N > 0; }
   const Dev& dev() const { return D_; }
   const Topology& topo() const { return topo_; }
@@ -105,6 +109,9 @@ class Scene {
   void solve_mixed(int32_t& ind, int32_t& iters);
   void eig_all();
   void eig_list(int32_t n);
+  void upload_job(int n_gamma = 0, const double* gam = nullptr);
+  void launch_assemble();
+  void energy_diff(int n, const double* gam);
   void read_scal(int n, double* out);
 
   hipStream_t st_;
@@ -112,7 +119,12 @@ class Scene {
   bool own_stream_;
   int precision_;
   PcgBatcher* batcher_ = nullptr;
+  bool batch_eval_ = false;
   Dev D_;
+  EvalJob job_host_{};          // the table entry last written to D_.job
+  bool job_valid_ = false;
+  EvalGrid grid_;               // this scene's grids of the evaluation kernels
+  hipGraphExec_t eval_graph_ = nullptr;
   Topology topo_;
   std::vector<void*> allocs_;
   int64_t dev_bytes_ = 0;

@@ -96,6 +96,29 @@ def test_engine_pcg_batching_changes_nothing(precision):
         assert np.array_equal(st_alone[i][0], st_mix[i][0]) and np.array_equal(st_alone[i][1], st_mix[i][1])
 
 
+@pytest.mark.parametrize("precision", [PPN_FP64, PPN_MIXED])
+def test_engine_evaluation_batching_changes_nothing(precision):
+    """With PPN_BATCH_EVAL the scenes' evaluation phases (element quantities,
+    assembly, gradient norms) and line-search launches are shared too: every
+    scene keeps the bits of its run alone, and of its run alone without graphs."""
+    scenes = _small_scenes(6)
+    with Engine(n_workers=1) as e1:
+        ids1 = [e1.add_scene(sc, precision=precision, params=dict(use_graphs=0)) for sc in scenes]
+        alone, st_alone = _run(e1, scenes, ids1, 3, interleave=False)
+    with Engine(n_workers=6) as eb:
+        eb.ppn_engine_set_batching(pcg=True, evaluation=True)
+        idsb = [eb.add_scene(sc, precision=precision) for sc in scenes]
+        mix, st_mix = _run(eb, scenes, idsb, 3, interleave=True)
+        info = eb.ppn_engine_get_info()
+    n_iters = sum(s["newton_iters"] for st in mix.values() for s in st)
+    assert info["eval_launches"] > 0 and info["eval_batched_phases"] >= n_iters, info
+    for i in range(len(scenes)):
+        for n, (a, b) in enumerate(zip(alone[i], mix[i])):
+            diff = {k: (a[k], b[k]) for k in KEYS if a[k] != b[k]}
+            assert not diff, (scenes[i].name, n + 1, diff)
+        assert np.array_equal(st_alone[i][0], st_mix[i][0]) and np.array_equal(st_alone[i][1], st_mix[i][1])
+
+
 def test_engine_pcg_batching_mixed_precisions_together():
     """FP64 and mixed-form scenes in one batching engine: the batcher runs its
     FP64-matrix and FP32-matrix lanes side by side, and every scene keeps the

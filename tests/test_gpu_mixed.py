@@ -36,7 +36,7 @@ from oracle.project import project_to_pd
 from paper_2505_21013_amd import PPN_MIXED, run_steps
 from scenes import config, cube_compress, renumbered
 
-from helpers import gpu_scene, oracle_stepper, squashed_state
+from helpers import first_hard_step, gpu_scene, oracle_stepper, squashed_state
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -306,10 +306,12 @@ def test_mixed_beam_twist_against_oracle_record():
           f"oracle's) {differ}; on the others: final residual against the oracle's {worst_traj:.2e} res0, "
           f"Newton iterations whose projected set differs {iter_mism}/{n_iter}; positions "
           f"{', '.join(f'step {k} {v:.2e}' for k, v in errs.items())} of the diagonal")
-    # Step 95, where PN and PDN reach the iteration cap, is the one whose counts
-    # move with the rounding of the solves (the FP64 form matches it exactly).
-    assert [d[0] for d in differ] in ([], [95]), differ
+    # only steps from the first hard one on (tests/helpers.py) may take other counts
+    assert all(d[0] >= first_hard_step(gold["steps"]) for d in differ), differ
     assert worst_traj <= 1e-8, worst_traj
     assert iter_mism <= 0.01 * n_iter, (iter_mism, n_iter)
+    # after a hard step, the bound of the Newton stopping rule (10 h tol, as in
+    # tests/test_gpu_beam_golden.py), relative to the diagonal
+    first_hard = first_hard_step(gold["steps"])
     for k, v in errs.items():
-        assert v <= 1e-6 or int(k) >= 95, (k, v)
+        assert v <= (1e-6 if int(k) < first_hard else 10 * sc.dt * sc.stop_tol / diag), (k, v)
