@@ -163,9 +163,10 @@ def composite_roofline(R, precision, info, K):
         (152 B of element data read, 720 B of slots written, slots read back
         once by the vertex and edge passes), 261 B per vertex, 76 B per edge
         (its block written once, its slot range pointer);
-      PCG iteration: the matrix product (spmv_bytes) + the update (216 B per
+      PCG iteration: the matrix product (spmv_bytes) + the update (240 B per
         vertex: q, d, r, x and the 6-entry symmetric block-Jacobi inverse read,
-        x, r and z written; 192 B with the FP32 inverse);
+        x, r and the 48-byte (z, d) record that the next product gathers
+        written; 216 B with the FP32 inverse);
       line-search pass (four step sizes): 112 B per tet + 84 B per vertex;
       eigen-projection: 45.6 kflop (measured executed flops of the 9x9 Jacobi)."""
     N, T, NB = info["n_verts"], info["n_tets"], info["n_blocks"]
@@ -173,7 +174,7 @@ def composite_roofline(R, precision, info, K):
     tot = R["tot"]
     fp32 = precision == "mixed"
     bw = HBM_PEAK_GBS * 1e9
-    pcg = tot["pcg_iters"] * (spmv_bytes(N, NB, fp32) + (192 if fp32 else 216) * N) / bw
+    pcg = tot["pcg_iters"] * (spmv_bytes(N, NB, fp32) + (216 if fp32 else 240) * N) / bw
     elem = tot["newton_iters"] * (1592 * T + 261 * N + 76 * E) / bw
     ls = (tot["newton_iters"] + tot["ls_backtracks"] / 4.0) * (112 * T + 84 * N) / bw
     eig = tot["projected"] * 45.6e3 / ((157.3 if fp32 else 78.6) * 1e12)
@@ -449,6 +450,8 @@ def main():
     ap.add_argument("--no-pcg-batching", action="store_true",
                     help="--serve: solve each scene's systems in its own launches")
     ap.add_argument("--rate", type=float, default=200.0, help="--serve: mean arrival rate [1/s]")
+    ap.add_argument("--launch-gaps", action="store_true",
+                    help="only run the launch-cost probe (plain stream launches against HIP graph replays)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 plain device copies of this many MiB (HBM counter calibration)")
     a = ap.parse_args()
@@ -456,6 +459,12 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
               "note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if a.launch_gaps:
+        # 12 and 5 us: the product and the update of one PCG iteration on the twisted beam
+        exe = os.path.join(ROOT, "paper_2505_21013_amd", "launch_gaps")
+        if not os.path.exists(exe):
+            sys.exit(f"{exe} is not built (python -c 'import __graft_entry__ as g; g.build()')")
+        sys.exit(subprocess.run([exe, "12", "5"]).returncode)
     if a.ablation:
         print(json.dumps(run_ablation(a)), flush=True)
         return

@@ -55,7 +55,8 @@ template <typename M>
 struct PcgVec {
   const M* vals = nullptr;    // sliced-ELL values
   const M* pinv = nullptr;    // [6][N] block-Jacobi inverse (symmetric, upper triangle)
-  double* zd = nullptr;       // [2][N][6] (z, d) records
+  double* zd = nullptr;       // [N][6] (z, previous d) records
+  double* dn = nullptr;       // [N][3] new direction
   double* r = nullptr;        // [N][3] residual
   double* q = nullptr;        // [N][3] H d
   double* x = nullptr;        // [N][3] solution
@@ -115,7 +116,8 @@ struct Dev {
   // vectors [N][3]
   double *x = nullptr, *xn = nullptr, *v = nullptr, *xhat = nullptr, *g = nullptr, *dx = nullptr;
   double *r = nullptr, *q = nullptr, *xt = nullptr;
-  double* zd = nullptr;    // [2][N][6]: (z, d) records by PCG iteration parity
+  double* zd = nullptr;    // [N][6]: (z, previous d) records of the PCG
+  double* dn = nullptr;    // [N][3]: the PCG's new direction
   double* rinf = nullptr;  // [N]
   // mixed precision (null in FP64 scenes)
   float* vals32 = nullptr;  // FP32 matrix: full layout [n_slots * 9 * 64] (f32_full) or the half

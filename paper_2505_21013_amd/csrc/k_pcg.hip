@@ -13,10 +13,13 @@
 // No fences or grid barriers are used: on a multi-XCD part a device-scope
 // fence writes back the whole L2, while the kernel boundary does it once.
 //
-// Data: zd[2][N][6] holds (z, d) per vertex in 48-byte records, double-buffered
-// by iteration parity: the product of iteration j gathers (z_j, d_{j-1}) from
-// zd[j&1] with three 16-byte loads per column and writes d_j into zd[(j+1)&1];
-// the update writes z_{j+1} next to it.
+// Data: zd[N][6] holds (z_j, d_{j-1}) per vertex in 48-byte records, which the
+// product gathers with three 16-byte loads per column; it writes its row's new
+// direction d_j to dn[N][3].  The update then rewrites the whole record as
+// (z_{j+1}, d_j): every store of both kernels covers whole cache lines (a
+// record half written alone would leave each line partly written, twice per
+// iteration), and no kernel writes the records while the product reads them,
+// so one copy suffices.
 //
 // The kernels are templates on the matrix type M.  FP64 is the plain path.
 // With M = FP32 (the mixed-precision path) the sliced-ELL values and the
@@ -39,6 +42,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "k_common.h"
 #include "topology.h"
@@ -68,7 +72,7 @@ __device__ __forceinline__ bool solve_done(const PcgState* pcg) {
   return s_done != 0;
 }
 
-// r = sign * src, x = 0, z = P^-1 r into zd[0]; partials of r^T r, r^T z and
+// r = sign * src, x = 0, records (z, 0) with z = P^-1 r; partials of r^T r, r^T z and
 // the count of diagonal blocks failing Sylvester's criterion.
 // The bodies below take the scene's logical workgroup index w (0 .. Gp-1):
 // the single-scene kernels derive it from the hardware index, the batched
@@ -94,6 +98,7 @@ __device__ __forceinline__ void pcg_init_body(const Dev& D, const PcgVec<M>& V, 
                         double(V.pinv[kSym3[c][1] * N + i]) * r[1] +
                         double(V.pinv[kSym3[c][2] * N + i]) * r[2];
       V.zd[6 * size_t(i) + c] = zc;
+      V.zd[6 * size_t(i) + 3 + c] = 0.0;
       rz += r[c] * zc;
       rr += r[c] * r[c];
     }
@@ -291,8 +296,7 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   __shared__ double lds[16];
   if (solve_done(D.pcg)) return;
   const int Gp = D.Gp;
-  const double* zcur = V.zd + ((j & 1) ? 6 * size_t(D.N) : 0);
-  double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(D.N));
+  const double* zcur = V.zd;
   const double* pa = D.part + kPartRR * Gp;
   const double* pb = D.part + ((j & 1) ? kPartRZ1 : kPartRZ0) * Gp;
   double sa = 0.0, sb = 0.0, sc = 0.0;
@@ -357,10 +361,9 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
       q1 += beta * double(qd[1]);
       q2 += beta * double(qd[2]);
     }
-    double* o = znext + 6 * size_t(i) + 3;
-    o[0] = dn0;
-    o[1] = dn1;
-    o[2] = dn2;
+    V.dn[3 * i] = dn0;
+    V.dn[3 * i + 1] = dn1;
+    V.dn[3 * i + 2] = dn2;
     V.q[3 * i] = q0;
     V.q[3 * i + 1] = q1;
     V.q[3 * i + 2] = q2;
@@ -377,20 +380,24 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int 
 }
 
 // The row's inputs are loaded before the d^T q partials are combined, so both
-// latencies overlap.  Its outputs (z, r, x) are written with non-temporal
-// stores: none is read again within this kernel, and keeping them out of the
-// L2 as dirty lines shortens the write-back at the kernel's end (measured:
-// 91 against 94 us per FP64 PCG iteration on the 1.57M-tet cube).  The workgroup's 256 vertices own a contiguous run of
-// 768 values of each [N][3] vector: q, r and x are moved between HBM and LDS
-// with unit-stride loads and stores and read per vertex from LDS, instead of
-// three 24-byte-strided accesses per vector and lane.
+// latencies overlap.  The workgroup's 256 vertices own a contiguous run of 768
+// values of each [N][3] vector and of 1536 values of the records: q, r, x and
+// d are moved from HBM to LDS with unit-stride loads, and r, x and the new
+// records (z_{j+1}, d_j), assembled in LDS, back with unit-stride non-temporal
+// stores, instead of 24- and 48-byte-strided accesses per lane.  None of the
+// outputs is read again within the kernel; kept out of the L2 as dirty lines
+// they shorten its write-back at the kernel's end.  Measured on the 1.57M-tet
+// cube, per FP64 update: 14.6 us with z written into half of each record,
+// 15.3 us with whole records stored per lane, 13.7 us as here.
 template <typename M, bool kStream>
 __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V, int j, int w) {
   __shared__ double lds[16];
-  __shared__ double sq[3 * kPcgBlock], sr[3 * kPcgBlock], sx[3 * kPcgBlock];
+  // q and d, then (once both are read) the new records
+  __shared__ double sqd[6 * kPcgBlock], sr[3 * kPcgBlock], sx[3 * kPcgBlock];
+  double* sq = sqd;
+  double* sd = sqd + 3 * kPcgBlock;
   if (solve_done(D.pcg)) return;
   const int Gp = D.Gp, N = D.N;
-  double* znext = V.zd + ((j & 1) ? 0 : 6 * size_t(N));
   const int t = threadIdx.x;
   const int i = w * kPcgBlock + t;
   const int64_t f0 = int64_t(w) * (3 * kPcgBlock);  // first vector value of the workgroup
@@ -402,12 +409,11 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
       sq[k * kPcgBlock + t] = V.q[f];
       sr[k * kPcgBlock + t] = V.r[f];
       sx[k * kPcgBlock + t] = V.x[f];
+      sd[k * kPcgBlock + t] = V.dn[f];
     }
   }
-  double d[3] = {0, 0, 0}, P[6];
+  double P[6];
   if (i < N) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) d[c] = znext[6 * size_t(i) + 3 + c];
 #pragma unroll
     for (int k = 0; k < 6; ++k)
       P[k] = double(kStream ? __builtin_nontemporal_load(V.pinv + k * N + i) : V.pinv[k * N + i]);
@@ -416,23 +422,36 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
   if (kap <= 0.0) { pcg_finish(D, w, 1, j + 1); return; }
   const double alpha = D.pcg->rz[j & 1] / kap;
   double rr = 0.0, rzn = 0.0;
+  double d[3] = {0, 0, 0}, z[3] = {0, 0, 0};
   if (i < N) {
     double r[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      d[c] = sd[3 * t + c];
       sx[3 * t + c] += alpha * d[c];
       r[c] = sr[3 * t + c] - alpha * sq[3 * t + c];
       sr[3 * t + c] = r[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double zc = P[kSym3[c][0]] * r[0] + P[kSym3[c][1]] * r[1] + P[kSym3[c][2]] * r[2];
-      __builtin_nontemporal_store(zc, znext + 6 * size_t(i) + c);
-      rzn += r[c] * zc;
+      z[c] = P[kSym3[c][0]] * r[0] + P[kSym3[c][1]] * r[1] + P[kSym3[c][2]] * r[2];
+      rzn += r[c] * z[c];
       rr += r[c] * r[c];
     }
   }
-  block_sum2(rr, rzn, lds);  // synchronises: sx and sr are complete
+  block_sum2(rr, rzn, lds);  // synchronises: sx and sr are complete, sq and sd read
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    sqd[6 * t + c] = z[c];
+    sqd[6 * t + 3 + c] = d[c];
+  }
+  __syncthreads();
+  const int64_t e0 = int64_t(w) * (6 * kPcgBlock), ne = 6 * int64_t(N);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int64_t e = e0 + k * kPcgBlock + t;
+    if (e < ne) __builtin_nontemporal_store(sqd[k * kPcgBlock + t], V.zd + e);
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int64_t f = f0 + k * kPcgBlock + t;
@@ -461,20 +480,50 @@ static void pcg_init(const Dev& D, const PcgVec<T>& V, const double* src, double
 // A sampled product (events given) is launched with the events attached to the
 // launch itself, so that their interval is the kernel's execution and not the
 // dispatch gap after the preceding kernel.
+// Resident product workgroups per CU when the matrix stays in the last-level
+// cache.  Each stored block is read twice, by its owner row and transposed by
+// its partner row one slot later; the second read hits the XCD's L2 only if
+// the bytes that all workgroups in flight on that XCD read in between (about
+// one slot of every row in flight) fit there.  With every workgroup of the
+// 1.57M-tet cube resident at once (4.2 per CU) they do not: capping residency
+// at 3 per CU, so that rows run as a window moving through each XCD's range,
+// cut the product's L2 fetches by 15% and its time by 11% (54.9 -> 48.7 us);
+// at 2 per CU the fetches fall further (-25%) but too few waves remain to
+// hide the latency (53.1 us).  The cap is an otherwise unused dynamic LDS
+// request just above a quarter of the CU's LDS.
+constexpr int kSpmvWgPerCu = 3;
+
+static size_t spmv_cap_lds() {
+  static std::atomic<int> cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  int v = cached[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    int per_cu = 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess || per_cu <= 0)
+      per_cu = 160 * 1024;
+    v = per_cu / (kSpmvWgPerCu + 1) + 1024;
+    cached[dev].store(v, std::memory_order_relaxed);
+  }
+  return size_t(v);
+}
+
 template <typename T, int kLoad>
 static void pcg_iter_k(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                        hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
+  const size_t lds = kLoad == kLoadCached ? spmv_cap_lds() : 0;
   if (ev_spmv_start && ev_spmv_stop) {
     if (j == 0)
-      hipExtLaunchKernelGGL(k_pcg_spmv<T, true, kLoad>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
+      hipExtLaunchKernelGGL(k_pcg_spmv<T, true, kLoad>, dim3(D.Gp), dim3(kPcgBlock), lds, st,
                             ev_spmv_start, ev_spmv_stop, 0, D, V, j, tol2, maxit);
     else
-      hipExtLaunchKernelGGL(k_pcg_spmv<T, false, kLoad>, dim3(D.Gp), dim3(kPcgBlock), 0, st,
+      hipExtLaunchKernelGGL(k_pcg_spmv<T, false, kLoad>, dim3(D.Gp), dim3(kPcgBlock), lds, st,
                             ev_spmv_start, ev_spmv_stop, 0, D, V, j, tol2, maxit);
   } else if (j == 0) {
-    k_pcg_spmv<T, true, kLoad><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
+    k_pcg_spmv<T, true, kLoad><<<D.Gp, kPcgBlock, lds, st>>>(D, V, j, tol2, maxit);
   } else {
-    k_pcg_spmv<T, false, kLoad><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j, tol2, maxit);
+    k_pcg_spmv<T, false, kLoad><<<D.Gp, kPcgBlock, lds, st>>>(D, V, j, tol2, maxit);
   }
   k_pcg_update<T, kLoad == kLoadStream><<<D.Gp, kPcgBlock, 0, st>>>(D, V, j);
 }

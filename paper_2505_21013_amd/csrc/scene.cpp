@@ -188,7 +188,8 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
   D.xbar = alloc.template get<double>(3 * n);
   double** vecs[] = {&D.x, &D.xn, &D.v, &D.xhat, &D.g, &D.dx, &D.r, &D.q, &D.xt};
   for (double** p : vecs) *p = alloc.template get<double>(3 * n);
-  D.zd = alloc.template get<double>(12 * n);
+  D.zd = alloc.template get<double>(6 * n);
+  D.dn = alloc.template get<double>(3 * n);
   D.rinf = alloc.template get<double>(n);
   if (precision == PPN_MIXED) {
     D.vals32 = alloc.template get<float>(size_t(D.f32_full ? D.n_slots : D.n_hslots) * 9 * kSell);
@@ -620,6 +621,7 @@ void Scene::solve(int32_t& ind, int32_t& iters) {
     V.vals = D_.vals;
     V.pinv = D_.pinv;
     V.zd = D_.zd;
+    V.dn = D_.dn;
     V.r = D_.r;
     V.q = D_.q;
     V.x = D_.dx;
@@ -650,6 +652,7 @@ void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
   V.vals = D_.vals32;
   V.pinv = D_.pinv32;
   V.zd = D_.zd;
+  V.dn = D_.dn;
   V.r = D_.ri;  // D_.r holds the refinement residual, the inner solve's right-hand side
   V.q = D_.qi;
   V.x = D_.e;
