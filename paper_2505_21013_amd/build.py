@@ -37,6 +37,25 @@ def _compile(src):
     return obj, warn
 
 
+PROBES = os.path.join(CSRC, "probes")
+
+
+def build_probes():
+    """Stand-alone measurement programs (csrc/probes/*.hip), one executable
+    each beside this file: not part of the library."""
+    out = []
+    for f in sorted(os.listdir(PROBES)):
+        if not f.endswith(".hip"):
+            continue
+        exe = os.path.join(HERE, os.path.splitext(f)[0])
+        cmd = [HIPCC, "-x", "hip", *[c for c in COMMON if c != "-fPIC"], os.path.join(PROBES, f), "-o", exe]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        out.append(exe)
+    return out
+
+
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
@@ -51,6 +70,7 @@ def build(verbose=True):
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probes()
     return LIB
 
 

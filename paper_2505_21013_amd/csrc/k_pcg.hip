@@ -230,9 +230,6 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
                                                        int g, int l, M qz[3], M qd[3]) {
   const int S = D.gslots[g];
   qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = M(0);
-  // Two slots in flight per lane, and each slot's column and value reference
-  // loaded one slot ahead: the value loads depend on the reference (measured on
-  // the 1.57M-tet cube: 55.5 us per FP64 product against 61.0 with neither).
   if (sizeof(M) == 4 && D.f32_full) {
     // full-layout FP32 copy: the block of slot s sits at its own position
 #pragma unroll 2
@@ -257,28 +254,51 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
     }
     return;
   }
-  // half storage (FP64, or its FP32 copy)
-  int2 nxt = S > 0 ? slot_colref(D, g, l) : make_int2(0, 0);
-#pragma unroll 2
-  for (int s = 0; s < S; ++s) {
-    const int2 cr = nxt;
-    if (s + 1 < S) nxt = slot_colref(D, (s + 1) * D.n_groups + g, l);
-    const int c = cr.x;
-    const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
-    const double2 a = p[0], b = p[1];
-    const M z0 = M(a.x), z1 = M(a.y), z2 = M(b.x);
-    M w[9];
-    load_block<kLoad>(vals, cr.y & kRefPosMask, w);
-    orient_block(cr.y, w);
-    qz[0] += block_row(w[0], w[1], w[2], z0, z1, z2);
-    qz[1] += block_row(w[3], w[4], w[5], z0, z1, z2);
-    qz[2] += block_row(w[6], w[7], w[8], z0, z1, z2);
-    if (with_d) {
-      const double2 e = p[2];
-      const M d0 = M(b.y), d1 = M(e.x), d2 = M(e.y);
-      qd[0] += block_row(w[0], w[1], w[2], d0, d1, d2);
-      qd[1] += block_row(w[3], w[4], w[5], d0, d1, d2);
-      qd[2] += block_row(w[6], w[7], w[8], d0, d1, d2);
+  // Half storage (FP64, or its FP32 copy): the slots in batches of kSlotBatch
+  // whose loads (column and reference one batch ahead, then records and
+  // blocks) are all issued before the batch is accumulated, in slot order.
+  // Measured on the 1.57M-tet cube (FP64, 3 / 2 resident workgroups per CU):
+  // one slot at a time with its reference loaded a slot ahead 49.1 / 53.1 us,
+  // batches of 2 48.9 / 48.0 us, of 4 47.5 / 46.9 us.
+  constexpr int kSlotBatch = 4;
+  int2 nx[kSlotBatch];
+#pragma unroll
+  for (int k = 0; k < kSlotBatch; ++k)
+    nx[k] = k < S ? slot_colref(D, k * D.n_groups + g, l) : make_int2(0, 0);
+  for (int s0 = 0; s0 < S; s0 += kSlotBatch) {
+    int2 cr[kSlotBatch];
+#pragma unroll
+    for (int k = 0; k < kSlotBatch; ++k) {
+      cr[k] = nx[k];
+      if (s0 + kSlotBatch + k < S) nx[k] = slot_colref(D, (s0 + kSlotBatch + k) * D.n_groups + g, l);
+    }
+    M w[kSlotBatch][9];
+    double2 ra[kSlotBatch], rb[kSlotBatch], re[kSlotBatch];
+#pragma unroll
+    for (int k = 0; k < kSlotBatch; ++k) {
+      if (s0 + k < S) {  // S is the group's: uniform over the wavefront
+        const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(cr[k].x));
+        ra[k] = p[0];
+        rb[k] = p[1];
+        if (with_d) re[k] = p[2];
+        load_block<kLoad>(vals, cr[k].y & kRefPosMask, w[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSlotBatch; ++k) {
+      if (s0 + k < S) {
+        orient_block(cr[k].y, w[k]);
+        const M z0 = M(ra[k].x), z1 = M(ra[k].y), z2 = M(rb[k].x);
+        qz[0] += block_row(w[k][0], w[k][1], w[k][2], z0, z1, z2);
+        qz[1] += block_row(w[k][3], w[k][4], w[k][5], z0, z1, z2);
+        qz[2] += block_row(w[k][6], w[k][7], w[k][8], z0, z1, z2);
+        if (with_d) {
+          const M d0 = M(rb[k].y), d1 = M(re[k].x), d2 = M(re[k].y);
+          qd[0] += block_row(w[k][0], w[k][1], w[k][2], d0, d1, d2);
+          qd[1] += block_row(w[k][3], w[k][4], w[k][5], d0, d1, d2);
+          qd[2] += block_row(w[k][6], w[k][7], w[k][8], d0, d1, d2);
+        }
+      }
     }
   }
 }
@@ -485,15 +505,16 @@ static void pcg_init(const Dev& D, const PcgVec<T>& V, const double* src, double
 // its partner row one slot later; the second read hits the XCD's L2 only if
 // the bytes that all workgroups in flight on that XCD read in between (about
 // one slot of every row in flight) fit there.  With every workgroup of the
-// 1.57M-tet cube resident at once (4.2 per CU) they do not: capping residency
-// at 3 per CU, so that rows run as a window moving through each XCD's range,
-// cut the product's L2 fetches by 15% and its time by 11% (54.9 -> 48.7 us);
-// at 2 per CU the fetches fall further (-25%) but too few waves remain to
-// hide the latency (53.1 us).  The cap is an otherwise unused dynamic LDS
-// request just above a quarter of the CU's LDS.
-constexpr int kSpmvWgPerCu = 3;
-
+// 1.57M-tet cube resident at once (4.2 per CU) they do not.  Capping residency,
+// so that rows run as a window moving through each XCD's range, cut the FP64
+// product's L2 fetches by 15% at 3 per CU and by 25% at 2 per CU; at 2 per CU
+// the batched slot loads above keep enough bytes in flight (measured, FP64:
+// 54.9 us uncapped, 47.5 us at 3, 46.9 us at 2).  The FP32 copy, with half the
+// bytes per slot, is best at 3 (34.8 us; 37.4 at 2).  The cap is an otherwise
+// unused dynamic LDS request just above 1/(cap + 1) of the CU's LDS.
+template <typename T>
 static size_t spmv_cap_lds() {
+  constexpr int kWgPerCu = sizeof(T) == 8 ? 2 : 3;
   static std::atomic<int> cached[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
@@ -503,7 +524,7 @@ static size_t spmv_cap_lds() {
     if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
             hipSuccess || per_cu <= 0)
       per_cu = 160 * 1024;
-    v = per_cu / (kSpmvWgPerCu + 1) + 1024;
+    v = per_cu / (kWgPerCu + 1) + 1024;
     cached[dev].store(v, std::memory_order_relaxed);
   }
   return size_t(v);
@@ -512,7 +533,7 @@ static size_t spmv_cap_lds() {
 template <typename T, int kLoad>
 static void pcg_iter_k(const Dev& D, const PcgVec<T>& V, int j, double tol2, int maxit,
                        hipStream_t st, hipEvent_t ev_spmv_start, hipEvent_t ev_spmv_stop) {
-  const size_t lds = kLoad == kLoadCached ? spmv_cap_lds() : 0;
+  const size_t lds = kLoad == kLoadCached ? spmv_cap_lds<T>() : 0;
   if (ev_spmv_start && ev_spmv_stop) {
     if (j == 0)
       hipExtLaunchKernelGGL(k_pcg_spmv<T, true, kLoad>, dim3(D.Gp), dim3(kPcgBlock), lds, st,
