@@ -44,3 +44,39 @@ def bsr_to_dense(rp, col, vals, n):
 def bsr_to_csr(rp, col, vals, n):
     import scipy.sparse as sp
     return sp.bsr_matrix((vals, col, rp), shape=(3 * n, 3 * n)).tocsr()
+
+
+# A time step on which the oracle itself needs this many Newton iterations or
+# more (ordinary steps take 4 to 15) is a hard step: the method is far from its
+# quadratic convergence there (PN and PDN reach the 100-iteration cap on such
+# steps of the twisted beam and of the compressed cubes), and its iteration
+# count moves with the rounding of the linear solves.  On the twisted beam's
+# step 95, kernels that differ only in their rounding (the accumulation order
+# of the matrix product, which products the compiler fuses into FMAs) take 97,
+# 98, 99 or 100 PPN iterations where the oracle takes 97.  Once two runs have
+# gone through a hard step along different Newton paths, their states agree only
+# to the Newton stopping rule.  Record comparisons hold every step from the
+# first hard step on to the same status and Newton and projection counts within
+# 5%, and the positions after them to the bound of the stopping rule; every
+# step before it to exact counts, projected sets and residuals.
+HARD_STEP_ITERS = 50
+
+
+def hard_step(oracle_newton_iters):
+    return oracle_newton_iters >= HARD_STEP_ITERS
+
+
+def first_hard_step(steps, key="newton_iters"):
+    """1-based index of the first hard step of a list of oracle step records
+    (a large number if there is none)."""
+    return min([n + 1 for n, o in enumerate(steps) if hard_step(o[key])] + [10 ** 9])
+
+
+def check_hard_step(tag, g, o):
+    """Counts of a hard step against the oracle's: same status, Newton and
+    projection counts within 5% (at least 3 iterations)."""
+    assert (g["status"] == "PPN_OK") == o["converged"], (tag, g["status"])
+    assert abs(g["newton_iters"] - o["newton_iters"]) <= max(3, 0.05 * o["newton_iters"]), \
+        (tag, g["newton_iters"], o["newton_iters"])
+    assert abs(g["projected"] - o["projected"]) <= 0.05 * max(o["projected"], 1), \
+        (tag, g["projected"], o["projected"])
