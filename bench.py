@@ -91,6 +91,16 @@ def cpu_baseline(cfg, per_step_counts):
             "host_cpus": c.get("host_cpus"), "extrapolation_check": EXTRAPOLATION_CHECK}
 
 
+def form_params(a):
+    """Scene parameters the command line overrides (None: the defaults)."""
+    prm = {}
+    if a.no_graphs:
+        prm["use_graphs"] = 0
+    if a.pcg_load_mode is not None:
+        prm["pcg_load_mode"] = a.pcg_load_mode
+    return prm or None
+
+
 def run_form(a, precision, torch, np):
     """Warm-up steps, reset to the initial state, then K timed steps."""
     from paper_2505_21013_amd import PPN_FP64, PPN_MIXED, scene_from
@@ -98,7 +108,7 @@ def run_form(a, precision, torch, np):
     sc = cube_compress(n=a.cells) if a.cells and a.config == 2 else config(a.config)
     stream = torch.cuda.current_stream().cuda_stream
     s = scene_from(sc, stream=stream, precision=PPN_MIXED if precision == "mixed" else PPN_FP64,
-                   params=dict(use_graphs=0) if a.no_graphs else None)
+                   params=form_params(a))
     info = s.ppn_scene_info()
     for n in range(1, a.warmup + 1):
         s.ppn_set_dirichlet(sc.dirichlet_ids, sc.targets(n))
@@ -430,6 +440,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graphs", action="store_true",
                     help="plain launches instead of the captured evaluation graph (use_graphs = 0)")
+    ap.add_argument("--pcg-load-mode", type=int, default=None, choices=[0, 1, 2],
+                    help="force how the PCG product loads the matrix (0 small, 1 cache-resident, "
+                         "2 streamed; default: chosen from its size)")
     ap.add_argument("--cells", type=int, default=None,
                     help="compressed cube of N^3 cells instead of 64^3 (size studies: no CPU baseline, and no "
                          "counter traffic, which was measured at 64^3)")

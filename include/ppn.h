@@ -90,10 +90,11 @@ typedef struct {
   int32_t eig_mirror;    /* 0: clamp eigenvalues to max(lambda, eps) (Eq. (4)); 1: mirror them,
                             max(|lambda|, eps) (the alternative filter of Sec. 2 and Sec. 5) */
   double k_dirichlet;   /* penalty stiffness [N/m] */
-  int32_t pcg_load_mode; /* -1 (default): chosen from the matrix size; 0 small, 1 cache-resident,
-                            2 streamed: forces how the PCG product of this scene's own solves loads
-                            the matrix.  Every mode gives the same bits; for tuning and tests.
-                            Batched engine launches always choose from the summed size. */
+  int32_t pcg_load_mode; /* -1 (default): chosen from the matrix size (0 up to 64 MB of values,
+                            else 1); 0 small, 1 ordinary loads with capped residency, 2 streamed
+                            with non-temporal loads: forces how the PCG product of this scene's own
+                            solves loads the matrix.  Every mode gives the same bits; for tuning and
+                            tests.  Batched engine launches always choose from the summed size. */
   int32_t use_graphs;    /* 1 (default): a scene stepped alone runs the kernels of each Newton
                             iteration's evaluation (element quantities, assembly, gradient
                             norms) as one HIP graph captured at its first use; 0: plain

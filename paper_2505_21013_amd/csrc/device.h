@@ -189,25 +189,22 @@ inline int64_t matrix_bytes_f32(const Dev& D) {
 // Load modes of the PCG product, chosen per launch from the size of the matrix
 // values (FP64, or the FP32 copy; summed over the jobs of a batched launch).
 // None changes the arithmetic or its order.
-//  * kLoadStream, above 224 MB: non-temporal loads, streamed from HBM so that
-//    the matrix does not evict the gathered vectors (measured per PCG
-//    iteration in FP64, cached against streamed: 23 / 26 us at 32^3 cells,
-//    37 / 41 us at 48^3, 52 / 59 us at 56^3 with its 200 MB matrix; 101 / 91 us
-//    at 64^3, 297 MB).
-//  * kLoadCached: ordinary loads; the matrix stays resident in the 256 MB
-//    last-level cache between iterations.
-//  * kLoadSmall, up to 64 MB: as kLoadCached with two slots in flight per lane
-//    in the FP64 product: few workgroups, bound by load latency (product
-//    13.7 -> 12.5 us on the 122,880-tet beam, 15.3 -> 14.2 us at 32^3; one
-//    slot stays faster at 48^3 and 56^3, 25.2 / 25.8 and 37.0 / 38.0 us).
+//  * kLoadSmall, up to 64 MB: ordinary loads; few workgroups, all resident.
+//  * kLoadCached, above 64 MB: ordinary loads, and a single scene's product
+//    keeps at most 2 (FP64) or 3 (FP32) workgroups resident per CU, so that the
+//    transposed read of a stored block meets its owner's read in the L2
+//    (k_pcg.hip).  It is the mode at every size above 64 MB, also far beyond
+//    the 256 MB last-level cache: on the 128^3 cube (FP64 values 1.07 GB) the
+//    FP64 product takes 532.7 us against 620.9 us with non-temporal loads, the
+//    FP32 one 375.8 against 427.4 us.
+//  * kLoadStream, only when forced (ppn_params.pcg_load_mode = 2): non-temporal
+//    loads, no cap.  With the matrix stored whole it was the better mode above
+//    224 MB (101 against 91 us per FP64 iteration on the 64^3 cube, 297 MB of
+//    values); with half storage a streamed block is fetched from HBM twice,
+//    by its owner row and by its partner row.
 constexpr int kLoadSmall = 0, kLoadCached = 1, kLoadStream = 2;
 constexpr int64_t kSmallMatrixBytes = int64_t(64) << 20;
-constexpr int64_t kCacheResidentMatrixBytes = int64_t(224) << 20;
-inline int load_mode(int64_t bytes) {
-  return bytes > kCacheResidentMatrixBytes ? kLoadStream
-         : bytes > kSmallMatrixBytes       ? kLoadCached
-                                           : kLoadSmall;
-}
+inline int load_mode(int64_t bytes) { return bytes > kSmallMatrixBytes ? kLoadCached : kLoadSmall; }
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
 void launch_precompute(const Dev& D, double rho, hipStream_t st);

@@ -132,11 +132,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_init(Dev D, PcgVec<M> V, cons
 // at slot*576 + 512 + lane: four 16-byte loads and one 8-byte load, contiguous
 // runs over a wavefront whose lanes read neighbouring positions (owned blocks;
 // lower blocks read from their column's row keep runs of up to 64 lanes).
-// kLoad == kLoadStream: the matrix is larger than the last-level cache and is
-// streamed with non-temporal loads that keep it from evicting the gathered
-// (z, d) records; smaller matrices are read with ordinary loads and stay
-// cache-resident from one iteration to the next.  The choice changes no
-// arithmetic.
+// kLoad == kLoadStream (forced only): the matrix is streamed with
+// non-temporal loads; otherwise ordinary loads, which let a block's second
+// (transposed) read hit the L2 and keep a matrix of up to the last-level
+// cache's size resident between iterations.  The choice changes no arithmetic.
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <int kLoad>
 __device__ __forceinline__ void load_block(const double* __restrict__ vals, int32_t pos, double w[9]) {

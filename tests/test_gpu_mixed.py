@@ -239,9 +239,8 @@ def test_mixed_cube64_solve_and_steps():
 
 def test_mixed_streamed_fp32_matrix_meets_fp64_residual():
     """An 80^3 compressed cube (3,072,000 tets) with the mixed product reading
-    its FP32 matrix with non-temporal loads (the mode of matrices beyond the
-    224 MiB kept resident in the last-level cache, forced here: the half-stored
-    FP32 matrix of this mesh is about 150 MB).  After one step, the mixed solve
+    its FP32 matrix with non-temporal loads (the streamed mode, forced: the
+    library reads matrices of this size with ordinary loads).  After one step, the mixed solve
     on the fully projected system meets the FP64 residual bound, checked with
     the library's FP64 gradient and product (both pinned to the oracle on other
     meshes), and gives a descent direction."""
