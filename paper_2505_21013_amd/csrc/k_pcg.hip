@@ -401,7 +401,10 @@ __global__ __launch_bounds__(kPcgBlock) void k_pcg_spmv(Dev D, PcgVec<M> V, int 
 // The row's inputs are loaded before the d^T q partials are combined, so both
 // latencies overlap.  The workgroup's 256 vertices own a contiguous run of 768
 // values of each [N][3] vector and of 1536 values of the records: q, r, x and
-// d are moved from HBM to LDS with unit-stride loads, and r, x and the new
+// d are moved from HBM to LDS with unit-stride non-temporal loads (read once;
+// kept out of the L2, they leave it to the next product: 47.0 -> 46.7 us per
+// product on the 1.57M-tet cube; the block-Jacobi inverse likewise made the
+// update slower, 13.7 -> 14.5 us, and keeps ordinary loads), and r, x and the new
 // records (z_{j+1}, d_j), assembled in LDS, back with unit-stride non-temporal
 // stores, instead of 24- and 48-byte-strided accesses per lane.  None of the
 // outputs is read again within the kernel; kept out of the L2 as dirty lines
@@ -425,10 +428,10 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
   for (int k = 0; k < 3; ++k) {
     const int64_t f = f0 + k * kPcgBlock + t;
     if (f < nf) {
-      sq[k * kPcgBlock + t] = V.q[f];
-      sr[k * kPcgBlock + t] = V.r[f];
-      sx[k * kPcgBlock + t] = V.x[f];
-      sd[k * kPcgBlock + t] = V.dn[f];
+      sq[k * kPcgBlock + t] = __builtin_nontemporal_load(V.q + f);
+      sr[k * kPcgBlock + t] = __builtin_nontemporal_load(V.r + f);
+      sx[k * kPcgBlock + t] = __builtin_nontemporal_load(V.x + f);
+      sd[k * kPcgBlock + t] = __builtin_nontemporal_load(V.dn + f);
     }
   }
   double P[6];
