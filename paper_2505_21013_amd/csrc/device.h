@@ -56,6 +56,8 @@ struct PcgVec {
   const M* vals = nullptr;    // sliced-ELL values
   const M* pinv = nullptr;    // [6][N] block-Jacobi inverse (symmetric, upper triangle)
   double* zd = nullptr;       // [N][6] (z, previous d) records
+  float* zd32 = nullptr;      // [N][6] the records rounded to FP32, gathered by the FP32 product
+                              // (M = float only)
   double* dn = nullptr;       // [N][3] new direction
   double* r = nullptr;        // [N][3] residual
   double* q = nullptr;        // [N][3] H d
@@ -117,6 +119,7 @@ struct Dev {
   double *x = nullptr, *xn = nullptr, *v = nullptr, *xhat = nullptr, *g = nullptr, *dx = nullptr;
   double *r = nullptr, *q = nullptr, *xt = nullptr;
   double* zd = nullptr;    // [N][6]: (z, previous d) records of the PCG
+  float* zd32 = nullptr;   // [N][6]: the same rounded to FP32 (mixed form)
   double* dn = nullptr;    // [N][3]: the PCG's new direction
   double* rinf = nullptr;  // [N]
   // mixed precision (null in FP64 scenes)

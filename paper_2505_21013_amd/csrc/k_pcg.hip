@@ -99,6 +99,10 @@ __device__ __forceinline__ void pcg_init_body(const Dev& D, const PcgVec<M>& V, 
                         double(V.pinv[kSym3[c][2] * N + i]) * r[2];
       V.zd[6 * size_t(i) + c] = zc;
       V.zd[6 * size_t(i) + 3 + c] = 0.0;
+      if constexpr (sizeof(M) == 4) {
+        V.zd32[6 * size_t(i) + c] = float(zc);
+        V.zd32[6 * size_t(i) + 3 + c] = 0.0f;
+      }
       rz += r[c] * zc;
       rr += r[c] * r[c];
     }
@@ -223,9 +227,34 @@ __device__ __forceinline__ void sell_row_product(const Dev& D, const double* __r
 // so that q = H (z + beta d_old) = qz + beta qd needs beta only at the end.
 // The arithmetic and the accumulation are in the matrix type M (FP32 for the
 // FP32 matrix: the gathered FP64 vectors are rounded on load).
+// The gathered record of column c as (z, d_old) in type M: the FP64 record,
+// or for the FP32 product its FP32 rounding (24 instead of 48 bytes; the same
+// values the FP64 record rounds to).
+template <typename M>
+struct Gathered { M z0, z1, z2, d0, d1, d2; };
+template <typename M>
+__device__ __forceinline__ Gathered<M> gather_record(const double* __restrict__ zd,
+                                                     const float* __restrict__ zd32, int c,
+                                                     bool with_d) {
+  Gathered<M> r;
+  if constexpr (sizeof(M) == 4) {
+    const float2* p = reinterpret_cast<const float2*>(zd32 + 6 * size_t(c));
+    const float2 a = p[0], b = p[1];
+    r.z0 = a.x; r.z1 = a.y; r.z2 = b.x; r.d0 = b.y;
+    if (with_d) { const float2 e = p[2]; r.d1 = e.x; r.d2 = e.y; } else { r.d1 = r.d2 = 0.0f; }
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
+    const double2 a = p[0], b = p[1];
+    r.z0 = a.x; r.z1 = a.y; r.z2 = b.x; r.d0 = b.y;
+    if (with_d) { const double2 e = p[2]; r.d1 = e.x; r.d2 = e.y; } else { r.d1 = r.d2 = 0.0; }
+  }
+  return r;
+}
+
 template <typename M, int kLoad>
 __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __restrict__ vals,
-                                                       const double* __restrict__ zd, bool with_d,
+                                                       const double* __restrict__ zd,
+                                                       const float* __restrict__ zd32, bool with_d,
                                                        int g, int l, M qz[3], M qd[3]) {
   const int S = D.gslots[g];
   qz[0] = qz[1] = qz[2] = qd[0] = qd[1] = qd[2] = M(0);
@@ -235,17 +264,15 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
     for (int s = 0; s < S; ++s) {
       const int slot = s * D.n_groups + g;
       const int c = D.col32[slot * kSell + l];
-      const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(c));
-      const double2 a = p[0], b = p[1];
-      const M z0 = M(a.x), z1 = M(a.y), z2 = M(b.x);
+      const Gathered<M> v = gather_record<M>(zd, zd32, c, with_d);
+      const M z0 = v.z0, z1 = v.z1, z2 = v.z2;
       M w[9];
       load_block<kLoad>(vals, slot * kSell + l, w);
       qz[0] += block_row(w[0], w[1], w[2], z0, z1, z2);
       qz[1] += block_row(w[3], w[4], w[5], z0, z1, z2);
       qz[2] += block_row(w[6], w[7], w[8], z0, z1, z2);
       if (with_d) {
-        const double2 e = p[2];
-        const M d0 = M(b.y), d1 = M(e.x), d2 = M(e.y);
+        const M d0 = v.d0, d1 = v.d1, d2 = v.d2;
         qd[0] += block_row(w[0], w[1], w[2], d0, d1, d2);
         qd[1] += block_row(w[3], w[4], w[5], d0, d1, d2);
         qd[2] += block_row(w[6], w[7], w[8], d0, d1, d2);
@@ -272,14 +299,11 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
       if (s0 + kSlotBatch + k < S) nx[k] = slot_colref(D, (s0 + kSlotBatch + k) * D.n_groups + g, l);
     }
     M w[kSlotBatch][9];
-    double2 ra[kSlotBatch], rb[kSlotBatch], re[kSlotBatch];
+    Gathered<M> rv[kSlotBatch];
 #pragma unroll
     for (int k = 0; k < kSlotBatch; ++k) {
       if (s0 + k < S) {  // S is the group's: uniform over the wavefront
-        const double2* p = reinterpret_cast<const double2*>(zd + 6 * size_t(cr[k].x));
-        ra[k] = p[0];
-        rb[k] = p[1];
-        if (with_d) re[k] = p[2];
+        rv[k] = gather_record<M>(zd, zd32, cr[k].x, with_d);
         load_block<kLoad>(vals, cr[k].y & kRefPosMask, w[k]);
       }
     }
@@ -287,12 +311,12 @@ __device__ __forceinline__ void sell_row_product_split(const Dev& D, const M* __
     for (int k = 0; k < kSlotBatch; ++k) {
       if (s0 + k < S) {
         orient_block(cr[k].y, w[k]);
-        const M z0 = M(ra[k].x), z1 = M(ra[k].y), z2 = M(rb[k].x);
+        const M z0 = rv[k].z0, z1 = rv[k].z1, z2 = rv[k].z2;
         qz[0] += block_row(w[k][0], w[k][1], w[k][2], z0, z1, z2);
         qz[1] += block_row(w[k][3], w[k][4], w[k][5], z0, z1, z2);
         qz[2] += block_row(w[k][6], w[k][7], w[k][8], z0, z1, z2);
         if (with_d) {
-          const M d0 = M(rb[k].y), d1 = M(re[k].x), d2 = M(re[k].y);
+          const M d0 = rv[k].d0, d1 = rv[k].d1, d2 = rv[k].d2;
           qd[0] += block_row(w[k][0], w[k][1], w[k][2], d0, d1, d2);
           qd[1] += block_row(w[k][3], w[k][4], w[k][5], d0, d1, d2);
           qd[2] += block_row(w[k][6], w[k][7], w[k][8], d0, d1, d2);
@@ -327,7 +351,7 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   const int i = w * kPcgBlock + threadIdx.x;
   const int g = i / kSell, l = i % kSell;
   M qz[3] = {0, 0, 0}, qd[3] = {0, 0, 0};
-  if (g < D.n_groups) sell_row_product_split<M, kLoad>(D, V.vals, zcur, !kFirst, g, l, qz, qd);
+  if (g < D.n_groups) sell_row_product_split<M, kLoad>(D, V.vals, zcur, V.zd32, !kFirst, g, l, qz, qd);
 
   sa = wave_sum(sa);
   sb = wave_sum(sb);
@@ -473,6 +497,14 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
   for (int k = 0; k < 6; ++k) {
     const int64_t e = e0 + k * kPcgBlock + t;
     if (e < ne) __builtin_nontemporal_store(sqd[k * kPcgBlock + t], V.zd + e);
+  }
+  if constexpr (sizeof(M) == 4) {
+    // the records rounded to FP32 for the next product's gathers
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int64_t e = e0 + k * kPcgBlock + t;
+      if (e < ne) __builtin_nontemporal_store(float(sqd[k * kPcgBlock + t]), V.zd32 + e);
+    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {

@@ -195,6 +195,7 @@ static void plan_buffers(Dev& D, int precision, A& alloc) {
     D.vals32 = alloc.template get<float>(size_t(D.f32_full ? D.n_slots : D.n_hslots) * 9 * kSell);
     if (D.f32_full) D.col32 = alloc.template get<int32_t>(size_t(D.n_slots) * kSell);
     D.pinv32 = alloc.template get<float>(6 * n);
+    D.zd32 = alloc.template get<float>(6 * n);
     D.e = alloc.template get<double>(3 * n);
     D.ri = alloc.template get<double>(3 * n);
     D.qi = alloc.template get<double>(3 * n);
@@ -652,6 +653,7 @@ void Scene::solve_mixed(int32_t& ind, int32_t& iters) {
   V.vals = D_.vals32;
   V.pinv = D_.pinv32;
   V.zd = D_.zd;
+  V.zd32 = D_.zd32;
   V.dn = D_.dn;
   V.r = D_.ri;  // D_.r holds the refinement residual, the inner solve's right-hand side
   V.q = D_.qi;
