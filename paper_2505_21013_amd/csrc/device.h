@@ -55,9 +55,9 @@ template <typename M>
 struct PcgVec {
   const M* vals = nullptr;    // sliced-ELL values
   const M* pinv = nullptr;    // [6][N] block-Jacobi inverse (symmetric, upper triangle)
-  double* zd = nullptr;       // [N][6] (z, previous d) records
-  float* zd32 = nullptr;      // [N][6] the records rounded to FP32, gathered by the FP32 product
-                              // (M = float only)
+  double* zd = nullptr;       // [N][6] (z, previous d) records; for M = float, z alone as [N][3]
+  float* zd32 = nullptr;      // [N][6] (M = float only) the records rounded to FP32, which the
+                              // FP32 product gathers
   double* dn = nullptr;       // [N][3] new direction
   double* r = nullptr;        // [N][3] residual
   double* q = nullptr;        // [N][3] H d

@@ -19,7 +19,8 @@
 // (z_{j+1}, d_j): every store of both kernels covers whole cache lines (a
 // record half written alone would leave each line partly written, twice per
 // iteration), and no kernel writes the records while the product reads them,
-// so one copy suffices.
+// so one copy suffices.  The mixed form gathers FP32 roundings of the records
+// instead (zd32) and keeps z alone, in FP64, as [N][3] for the rows' own use.
 //
 // The kernels are templates on the matrix type M.  FP64 is the plain path.
 // With M = FP32 (the mixed-precision path) the sliced-ELL values and the
@@ -97,11 +98,13 @@ __device__ __forceinline__ void pcg_init_body(const Dev& D, const PcgVec<M>& V, 
       const double zc = double(V.pinv[kSym3[c][0] * N + i]) * r[0] +
                         double(V.pinv[kSym3[c][1] * N + i]) * r[1] +
                         double(V.pinv[kSym3[c][2] * N + i]) * r[2];
-      V.zd[6 * size_t(i) + c] = zc;
-      V.zd[6 * size_t(i) + 3 + c] = 0.0;
       if constexpr (sizeof(M) == 4) {
+        V.zd[3 * size_t(i) + c] = zc;
         V.zd32[6 * size_t(i) + c] = float(zc);
         V.zd32[6 * size_t(i) + 3 + c] = 0.0f;
+      } else {
+        V.zd[6 * size_t(i) + c] = zc;
+        V.zd[6 * size_t(i) + 3 + c] = 0.0;
       }
       rz += r[c] * zc;
       rr += r[c] * r[c];
@@ -392,14 +395,34 @@ __device__ __forceinline__ void pcg_spmv_body(const Dev& D, const PcgVec<M>& V, 
   }
   double kap = 0.0;
   if (i < D.N) {
-    const double2* p = reinterpret_cast<const double2*>(zcur + 6 * size_t(i));
-    const double2 a = p[0], b = p[1], e = p[2];
-    double dn0 = a.x, dn1 = a.y, dn2 = b.x;
+    // the row's own z_j and d_{j-1}: from its record, or in the mixed form
+    // (whose gathers read the FP32 records) from z [N][3] and this vector
+    double z0, z1, z2, o0 = 0.0, o1 = 0.0, o2 = 0.0;
+    if constexpr (sizeof(M) == 4) {
+      z0 = zcur[3 * i];
+      z1 = zcur[3 * i + 1];
+      z2 = zcur[3 * i + 2];
+      if (!kFirst) {
+        o0 = V.dn[3 * i];
+        o1 = V.dn[3 * i + 1];
+        o2 = V.dn[3 * i + 2];
+      }
+    } else {
+      const double2* p = reinterpret_cast<const double2*>(zcur + 6 * size_t(i));
+      const double2 a = p[0], b = p[1], e = p[2];
+      z0 = a.x;
+      z1 = a.y;
+      z2 = b.x;
+      o0 = b.y;
+      o1 = e.x;
+      o2 = e.y;
+    }
+    double dn0 = z0, dn1 = z1, dn2 = z2;
     double q0 = double(qz[0]), q1 = double(qz[1]), q2 = double(qz[2]);
     if (!kFirst) {
-      dn0 += beta * b.y;
-      dn1 += beta * e.x;
-      dn2 += beta * e.y;
+      dn0 += beta * o0;
+      dn1 += beta * o1;
+      dn2 += beta * o2;
       q0 += beta * double(qd[0]);
       q1 += beta * double(qd[1]);
       q2 += beta * double(qd[2]);
@@ -493,17 +516,25 @@ __device__ __forceinline__ void pcg_update_body(const Dev& D, const PcgVec<M>& V
   }
   __syncthreads();
   const int64_t e0 = int64_t(w) * (6 * kPcgBlock), ne = 6 * int64_t(N);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int64_t e = e0 + k * kPcgBlock + t;
-    if (e < ne) __builtin_nontemporal_store(sqd[k * kPcgBlock + t], V.zd + e);
-  }
   if constexpr (sizeof(M) == 4) {
-    // the records rounded to FP32 for the next product's gathers
+    // mixed form: z as [N][3] for the rows' own use, and the records rounded
+    // to FP32 for the next product's gathers
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int idx = k * kPcgBlock + t;
+      const int64_t f = f0 + idx;
+      if (f < nf) __builtin_nontemporal_store(sqd[6 * (idx / 3) + idx % 3], V.zd + f);
+    }
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const int64_t e = e0 + k * kPcgBlock + t;
       if (e < ne) __builtin_nontemporal_store(float(sqd[k * kPcgBlock + t]), V.zd32 + e);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int64_t e = e0 + k * kPcgBlock + t;
+      if (e < ne) __builtin_nontemporal_store(sqd[k * kPcgBlock + t], V.zd + e);
     }
   }
 #pragma unroll
