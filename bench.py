@@ -38,11 +38,14 @@ def spmv_bytes(N, NB, fp32=False):
     is stored once (half storage): every stored block, the N diagonal and the
     E = (NB - N) / 2 edge blocks, is read once (72 B; 36 B for the FP32 matrix
     of the mixed form); every block of the full pattern costs its column and
-    value reference (8 B); each 64-row group its slot count (4 B); per vertex
-    the gathered z and previous direction are read and the new direction and
-    the product written (24 B each; the vectors are FP64 in both forms)."""
+    value reference (8 B); each 64-row group its slot count (4 B).  Per vertex,
+    FP64: its 48-byte (z, d_old) record gathered once, the new direction and
+    the product written (24 B each); mixed form: its 24-byte FP32 record
+    gathered once, its own FP64 z and d_old read (24 B each), the new direction
+    and the product written."""
     E = (NB - N) // 2
-    return 8 * NB + (36 if fp32 else 72) * (N + E) + 4 * ((N + 63) // 64) + 4 * 24 * N
+    per_vertex = 5 * 24 if fp32 else 4 * 24
+    return 8 * NB + (36 if fp32 else 72) * (N + E) + 4 * ((N + 63) // 64) + per_vertex * N
 
 
 def measured_traffic(fp32=False):

@@ -13,6 +13,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
@@ -36,8 +37,8 @@ class EvalBatcher {
   explicit EvalBatcher(int device);
   ~EvalBatcher();
   void run(const EvalJob& job, int kind);  // kind 0: evaluation, 1: line search; blocks
-  int64_t launches() const { return launches_; }  // shared phase launches
-  int64_t jobs() const { return jobs_; }          // scene phases carried by them
+  int64_t launches() const { return launches_.load(); }  // shared phase launches
+  int64_t jobs() const { return jobs_.load(); }          // scene phases carried by them
 
  private:
   struct Req {
@@ -54,7 +55,8 @@ class EvalBatcher {
   EvalJob* d_tab_ = nullptr;
   EvalJob* h_tab_ = nullptr;
   size_t cap_ = 0;
-  int64_t launches_ = 0, jobs_ = 0;
+  // written by the batcher thread, read by any (engine statistics)
+  std::atomic<int64_t> launches_{0}, jobs_{0};
   std::mutex mu_;
   std::condition_variable cv_, cv_done_;
   std::deque<Req*> q_;
@@ -76,8 +78,8 @@ class PcgBatcher {
              int maxit, int32_t& ind, int32_t& iters);
   void solve(const Dev& D, const PcgVec<float>& V, const double* src, double sign, double rtol,
              int maxit, int32_t& ind, int32_t& iters);
-  int64_t batches() const { return batches_; }  // chunks launched
-  int64_t solves() const { return solves_; }     // solves handed back
+  int64_t batches() const { return batches_.load(); }  // chunks launched
+  int64_t solves() const { return solves_.load(); }     // solves handed back
 
  private:
   struct Job {
@@ -133,7 +135,7 @@ class PcgBatcher {
   EvalBatcher eval_;
   hipStream_t st_ = nullptr;
   Lane lanes_[2];  // FP64 matrix, FP32 matrix
-  int64_t batches_ = 0, solves_ = 0;
+  std::atomic<int64_t> batches_{0}, solves_{0};  // as EvalBatcher's counters
   uint64_t next_id_ = 1;
   std::unordered_map<uint64_t, Job*> live_;  // batcher thread only
   std::mutex mu_;
