@@ -30,7 +30,7 @@ from .pcg import pcg_block_jacobi
 from .project import project_to_pd
 
 
-def sample_costs(sc, n_sample=786432, n_proj=150000, pcg_iters=60):
+def sample_costs(sc, n_sample=1572864, n_proj=300000, pcg_iters=100):
     stp = Stepper(sc.X, sc.tets, sc.E, sc.nu, sc.rho, sc.dt, sc.gravity, sc.dirichlet_ids,
                   Params(), x0=sc.x0, v0=sc.v0)
     stp.set_targets(sc.targets(1))
@@ -96,7 +96,7 @@ def cpu_model():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--n-sample", type=int, default=786432)
+    ap.add_argument("--n-sample", type=int, default=1572864)
     ap.add_argument("--cpu", type=int, default=None, help="pin the process to this core")
     a = ap.parse_args()
     if a.cpu is not None:
