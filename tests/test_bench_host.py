@@ -15,8 +15,11 @@ def test_product_bytes_per_launch():
     NB = N + 2 * E
     assert NB == 4018753
     assert bench.spmv_bytes(N, NB, False) == 8 * NB + 72 * (N + E) + 4 * 4292 + 96 * N
-    assert bench.spmv_bytes(N, NB, True) == 8 * NB + 36 * (N + E) + 4 * 4292 + 96 * N
+    # mixed form: 24 B more per row (the FP32 record is gathered, the row's own
+    # FP64 z and d are read from their vectors)
+    assert bench.spmv_bytes(N, NB, True) == 8 * NB + 36 * (N + E) + 4 * 4292 + 120 * N
     assert round(bench.spmv_bytes(N, NB, False) / 1e6, 1) == 213.1
+    assert round(bench.spmv_bytes(N, NB, True) / 1e6, 1) == 142.4
 
 
 def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
@@ -40,11 +43,18 @@ def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     assert bench.measured_traffic(False) is None and bench.measured_traffic(True) is None
 
 
-def test_committed_traffic_is_close_to_the_algorithmic_bytes():
+def test_committed_traffic_is_within_the_design_bound():
     """When the committed summary was taken on the current kernel source, its
-    traffic is within 20% above the algorithmic bytes (no wasted re-reads)."""
-    fp64 = bench.measured_traffic(False)
-    if fp64 is None:
-        import pytest
-        pytest.skip("the committed counter summary predates the current kernel source")
-    assert 1.0 <= fp64 / bench.spmv_bytes(274625, 4018753, False) < 1.2
+    traffic lies between the algorithmic bytes and those plus one more read of
+    every stored edge block: each is read by its owner row and, transposed, by
+    its partner row, the second read hitting the L2 or not.  More than that
+    would be re-reads the design does not account for."""
+    N, E = 274625, 1872064
+    NB = N + 2 * E
+    for fp32, entry in ((False, 72), (True, 36)):
+        t = bench.measured_traffic(fp32)
+        if t is None:
+            import pytest
+            pytest.skip("the committed counter summary predates the current kernel source")
+        alg = bench.spmv_bytes(N, NB, fp32)
+        assert alg <= t <= alg + entry * E, (fp32, t, alg)
