@@ -15,6 +15,13 @@ Run from the repository root, one process per (n, mode):
 With "ids", every Newton iteration also stores its projected element ids
 (ascending), so that a run can count the elements on which its projected set
 differs from the oracle's.
+
+With "renumber SEED", the oracle steps the same scene numbered at random
+(scenes.renumbered) and writes cube<n>_compress_<MODE>_renum<SEED>.json with its
+per-step counts only: the same mathematics summed in other orders, which shows
+from which step on the scene's Newton path is decided by rounding.
+
+    python tests/golden/make_compress_golden.py 32 PPN 46 renumber 1
 """
 import json
 import os
@@ -27,7 +34,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
-from scenes import cube_compress  # noqa: E402
+from scenes import cube_compress, renumbered  # noqa: E402
 
 SAMPLE = 200  # vertices whose positions are stored after every step
 
@@ -70,5 +77,26 @@ def main(n, mode, steps, with_ids=False):
     oracle.run_scene(sc, mode, n_steps=steps, trace=True, callback=cb)
 
 
+def main_renumbered(n, mode, steps, seed):
+    sc = renumbered(cube_compress(n=n, n_steps=50, ramp_steps=50), seed)
+    path = os.path.join(HERE, f"cube{n}_compress_{mode}_renum{seed}.json")
+    out = {"scene": f"renumbered(cube_compress(n={n}, n_steps=50, ramp_steps=50), {seed})", "mode": mode,
+           "steps": []}
+
+    def cb(k, s, st):
+        out["steps"].append(dict(newton_iters=st.newton_iters, projected=st.projected,
+                                 inner_rounds=st.inner_rounds, converged=bool(st.converged)))
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(out, f)
+        os.replace(tmp, path)
+        print(mode, "renumbered", seed, k, st.newton_iters, st.projected, bool(st.converged), flush=True)
+
+    oracle.run_scene(sc, mode, n_steps=steps, callback=cb)
+
+
 if __name__ == "__main__":
-    main(int(sys.argv[1]), sys.argv[2], int(sys.argv[3]), len(sys.argv) > 4 and sys.argv[4] == "ids")
+    if len(sys.argv) > 5 and sys.argv[4] == "renumber":
+        main_renumbered(int(sys.argv[1]), sys.argv[2], int(sys.argv[3]), int(sys.argv[5]))
+    else:
+        main(int(sys.argv[1]), sys.argv[2], int(sys.argv[3]), len(sys.argv) > 4 and sys.argv[4] == "ids")
