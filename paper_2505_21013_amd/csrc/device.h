@@ -72,6 +72,7 @@ struct Dev {
   int32_t G = 0;          // workgroups of the assembly / reduction kernels (fixed per scene)
   int32_t rows_per_wg = 0;  // vertex chunk per workgroup of those kernels
   int32_t Gp = 0;         // workgroups of the PCG kernels (multiple of 8; 256 rows each)
+  int32_t spmv_panel = 0; // panel length of the cache-resident product's workgroup order (0: none)
   int32_t pcg_load = -1;  // load mode of the PCG product (kLoad*), -1: chosen from the size
   int32_t n_groups = 0;   // 64-row groups of the sliced-ELL matrix
   int64_t n_slots = 0;    // smax * n_groups (slot-major block rows of the full pattern)

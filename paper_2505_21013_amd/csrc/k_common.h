@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "wg_order.h"
 
 namespace ppn {
 
@@ -86,6 +87,11 @@ constexpr int kSym3[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 // neighbouring rows then share an L2.  Requires G % 8 == 0.
 __device__ inline int xcd_chunk(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
 __device__ inline int logical_wg(int G) { return xcd_chunk(blockIdx.x, G); }
+
+__device__ inline int logical_wg_panels(int G, int P) {
+  const int b = blockIdx.x, C = G >> 3;
+  return (b & 7) * C + panel_order(b >> 3, C, P);
+}
 
 // The job of a shared launch that owns this workgroup (largest range start <=
 // blockIdx.x, by binary search over the table) and the workgroup's index

@@ -153,6 +153,19 @@ static void geometry(Dev& D, const Topology& t) {
   D.by_distance = t.by_distance ? 1 : 0;
   D.f32_full = t.by_distance ? 0 : 1;
   D.Gp = ((D.n_groups + 3) / 4 + 7) / 8 * 8;
+  // Panel length of the product's workgroup order (k_common.h panel_order):
+  // the median over rows of the distance to the farthest lower column, in
+  // 256-row workgroups, so that a row and its farthest partners run together.
+  std::vector<int32_t> far;
+  far.reserve(size_t(N));
+  for (int32_t i = 0; i < N; ++i)
+    if (t.row_ptr[i + 1] > t.row_ptr[i] && t.col[t.row_ptr[i]] < i) far.push_back(i - t.col[t.row_ptr[i]]);
+  D.spmv_panel = 0;
+  if (!far.empty()) {
+    std::nth_element(far.begin(), far.begin() + far.size() / 2, far.end());
+    const int32_t p = (far[far.size() / 2] + 128) / 256;
+    D.spmv_panel = p >= 2 ? p : 0;
+  }
 }
 
 // Every device buffer of a scene, in one place.  A::get<T>(count) either

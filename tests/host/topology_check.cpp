@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include "topology.h"
+#include "wg_order.h"
 using namespace ppn;
 static int fails = 0;
 #define CHECK(c) do { if (!(c)) { std::printf("FAIL %s:%d %s\n", __FILE__, __LINE__, #c); ++fails; } } while (0)
@@ -135,6 +136,17 @@ int main() {
     }
     check_mesh(N, tets, trial % 3 == 0 ? kSlotOrderAuto : trial % 3 == 1 ? kSlotOrderCsr : kSlotOrderDistance);
   }
+  // the product's panel order is a bijection of every XCD chunk
+  for (int C = 1; C <= 300; ++C)
+    for (int P = -1; P <= C + 2; ++P) {
+      std::vector<int> hit(C, 0);
+      for (int k = 0; k < C; ++k) {
+        const int w = panel_order(k, C, P);
+        if (w >= 0 && w < C) ++hit[w];
+        else CHECK(w >= 0 && w < C);
+      }
+      for (int w = 0; w < C; ++w) CHECK(hit[w] == 1);
+    }
   Topology t; std::string err;
   CHECK(!build_topology(0, 1, nullptr, t, err));
   int32_t one[4] = {0, 1, 2, 3};

@@ -3,7 +3,9 @@ and the sliced-ELL positions built by csrc/topology.cpp, checked against brute
 force on 300 random meshes (including out-of-range and repeated vertex
 indices and vertices outside every tetrahedron, which must be refused) by
 tests/host/topology_check.cpp, compiled with g++ and run under
-AddressSanitizer and UndefinedBehaviorSanitizer when the toolchain has them."""
+AddressSanitizer and UndefinedBehaviorSanitizer when the toolchain has them;
+the same program checks that the PCG product's panel order of workgroups
+(csrc/wg_order.h) is a bijection of every chunk size and panel length."""
 import os
 import shutil
 import subprocess
