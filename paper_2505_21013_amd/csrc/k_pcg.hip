@@ -580,13 +580,15 @@ static void pcg_init(const Dev& D, const PcgVec<T>& V, const double* src, double
 // 1.57M-tet cube resident at once (4.2 per CU) they do not.  Capping residency,
 // so that rows run as a window moving through each XCD's range, cut the FP64
 // product's L2 fetches by 15% at 3 per CU and by 25% at 2 per CU; at 2 per CU
-// the batched slot loads above keep enough bytes in flight (measured, FP64:
-// 54.9 us uncapped, 47.5 us at 3, 46.9 us at 2).  The FP32 copy, with half the
-// bytes per slot, is best at 3 (34.8 us; 37.4 at 2).  The cap is an otherwise
-// unused dynamic LDS request just above 1/(cap + 1) of the CU's LDS.
+// the batched slot loads above keep enough bytes in flight (measured, FP64 in
+// row order: 54.9 us uncapped, 47.5 us at 3, 46.9 us at 2).  With the panel
+// order of the FP64 product the partners' reads meet anyway, and 3 per CU is
+// better again (45.2 against 45.7 us at 2); the FP32 copy, with half the
+// bytes per slot, is best at 3 too (34.8 us; 37.4 at 2).  The cap is an
+// otherwise unused dynamic LDS request just above 1/(cap + 1) of the CU's LDS.
 template <typename T>
 static size_t spmv_cap_lds() {
-  constexpr int kWgPerCu = sizeof(T) == 8 ? 2 : 3;
+  constexpr int kWgPerCu = 3;
   static std::atomic<int> cached[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
