@@ -26,9 +26,10 @@ code (2 rtol |g_{k-1}| between two codes whose Krylov iterates round
 differently), and g_k inherits the difference through the nonlinearity of the
 energy (the largest difference is printed, relative to |g|_2 itself and to the
 step's initial residual, which the Dirichlet penalty dominates at 4e7).  From
-it on: the same status (in particular no convergence at steps 45 and 46), and
-Newton and projection counts within the oracle runs' spread widened by
-max(3, 5%)."""
+it on: a status that one of the three oracle runs shows (at step 44 one
+renumbered run ends at the cap where the others converge), no convergence
+where none of them converges (steps 45 and 46), and Newton and projection
+counts within the oracle runs' spread widened by max(3, 5%)."""
 import json
 import os
 
@@ -77,6 +78,7 @@ def test_cube32_breakdown_matches_the_oracle_record():
     runs = [[(o["newton_iters"], o["projected"]) for o in steps]]
     for r in renum:
         runs.append([(o["newton_iters"], o["projected"]) for o in r])
+    converged = [{bool(r[n]["converged"]) for r in [steps] + renum} for n in range(len(steps))]
     # first step whose counts the oracle's own renumbered runs change, or the first hard step
     differ = [n + 1 for n in range(len(steps)) if any(r[n] != runs[0][n] for r in runs[1:])]
     first_hard = min([first_hard_step(steps)] + differ[:1])
@@ -90,8 +92,8 @@ def test_cube32_breakdown_matches_the_oracle_record():
         print(f"cube32 step {n + 1}: {g['status']} newton {g['newton_iters']} (oracle {o['newton_iters']}) "
               f"projected {g['projected']} (oracle {o['projected']}) positions {err:.2e} of the diagonal")
         if n + 1 >= first_hard:
-            # the same status; counts within the oracle's own spread, widened by max(3, 5%)
-            assert (g["status"] == "PPN_OK") == o["converged"], (tag, g["status"])
+            # a status some oracle run shows; counts within their spread, widened by max(3, 5%)
+            assert (g["status"] == "PPN_OK") in converged[n], (tag, g["status"], converged[n])
             for k, key in enumerate(("newton_iters", "projected")):
                 lo, hi = min(r[n][k] for r in runs), max(r[n][k] for r in runs)
                 slack = max(3, 0.05 * hi)
@@ -116,6 +118,6 @@ def test_cube32_breakdown_matches_the_oracle_record():
           f"step's initial residual, {worst_own:.2e} of the oracle's |g|_2 itself; largest difference "
           f"{worst[0]:.2f} rtol |g_(k-1)| (step {worst[1]}, iteration {worst[2]})")
     assert worst[0] <= 10, worst
-    # the breakdown: the last two steps end at the cap in both codes
+    # the breakdown: the last two steps end at the cap in every oracle run and on the GPU
+    assert [converged[n] for n in (44, 45)] == [{False}, {False}]
     assert [s["status"] for s in stats[44:46]] == ["PPN_WARN_NOT_CONVERGED"] * 2
-    assert [o["converged"] for o in steps[44:46]] == [False, False]
