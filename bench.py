@@ -101,6 +101,8 @@ def form_params(a):
         prm["use_graphs"] = 0
     if a.pcg_load_mode is not None:
         prm["pcg_load_mode"] = a.pcg_load_mode
+    if a.eps_clamp is not None:
+        prm["eps_clamp"] = a.eps_clamp
     return prm or None
 
 
@@ -446,6 +448,9 @@ def main():
     ap.add_argument("--pcg-load-mode", type=int, default=None, choices=[0, 1, 2],
                     help="force how the PCG product loads the matrix (0 small, 1 cache-resident, "
                          "2 streamed; default: chosen from its size)")
+    ap.add_argument("--eps-clamp", type=float, default=None,
+                    help="eigenvalue clamp eps (default 1e-8, Sec. 5.1); the level the projection lifts the "
+                         "negative and the three translational zero eigenvalues to")
     ap.add_argument("--cells", type=int, default=None,
                     help="compressed cube of N^3 cells instead of 64^3 (size studies: no CPU baseline, and no "
                          "counter traffic, which was measured at 64^3)")
@@ -535,6 +540,8 @@ def main():
                    "n_verts": info["n_verts"], "n_blocks": info["n_blocks"],
                    "parallelism": "single GPU"},
     }
+    if form_params(a):
+        out["config"]["params"] = form_params(a)
     out.update(summary(R, K, info, np))
     cfg = a.config if not a.cells else None
     out["roofline"] = roofline(R, headline, info, cfg)
