@@ -58,3 +58,13 @@ def test_committed_traffic_is_within_the_design_bound():
             pytest.skip("the committed counter summary predates the current kernel source")
         alg = bench.spmv_bytes(N, NB, fp32)
         assert alg <= t <= alg + entry * E, (fp32, t, alg)
+
+
+def test_scene_parameter_overrides():
+    """Command-line overrides reach the scene parameters, and only when given
+    (the default run uses the library's defaults)."""
+    import argparse
+    base = dict(no_graphs=False, pcg_load_mode=None, eps_clamp=None)
+    assert bench.form_params(argparse.Namespace(**base)) is None
+    got = bench.form_params(argparse.Namespace(**dict(base, eps_clamp=1e-12, pcg_load_mode=2, no_graphs=True)))
+    assert got == {"eps_clamp": 1e-12, "pcg_load_mode": 2, "use_graphs": 0}
