@@ -195,12 +195,13 @@ inline int64_t matrix_bytes_f32(const Dev& D) {
 // None changes the arithmetic or its order.
 //  * kLoadSmall, up to 64 MB: ordinary loads; few workgroups, all resident.
 //  * kLoadCached, above 64 MB: ordinary loads, and a single scene's product
-//    keeps at most 2 (FP64) or 3 (FP32) workgroups resident per CU, so that the
-//    transposed read of a stored block meets its owner's read in the L2
-//    (k_pcg.hip).  It is the mode at every size above 64 MB, also far beyond
-//    the 256 MB last-level cache: on the 128^3 cube (FP64 values 1.07 GB) the
-//    FP64 product takes 532.7 us against 620.9 us with non-temporal loads, the
-//    FP32 one 375.8 against 427.4 us.
+//    keeps at most 3 workgroups resident per CU (the FP64 product runs its
+//    workgroups in panel order, wg_order.h), so that the transposed read of a
+//    stored block meets its owner's read in the L2 (k_pcg.hip).  It is the
+//    mode at every size above 64 MB, also far beyond the 256 MB last-level
+//    cache: on the 128^3 cube (FP64 values 1.07 GB) the FP64 product took
+//    532.7 us this way against 620.9 us with non-temporal loads (469 us with
+//    the panel order), the FP32 one 375.8 against 427.4 us.
 //  * kLoadStream, only when forced (ppn_params.pcg_load_mode = 2): non-temporal
 //    loads, no cap.  With the matrix stored whole it was the better mode above
 //    224 MB (101 against 91 us per FP64 iteration on the 64^3 cube, 297 MB of
