@@ -473,6 +473,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="--serve: mean arrival rate [1/s]")
     ap.add_argument("--launch-gaps", action="store_true",
                     help="only run the launch-cost probe (plain stream launches against HIP graph replays)")
+    ap.add_argument("--read-bw-mib", type=int, default=0,
+                    help="run the plain streaming read (csrc/probes/read_bw.hip) over this many MiB and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 5 plain device copies of this many MiB (HBM counter calibration)")
     a = ap.parse_args()
@@ -480,6 +482,12 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU layout is a design "
               "note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if a.read_bw_mib:
+        # HBM read rate of a plain streaming kernel over a resident buffer
+        exe = os.path.join(ROOT, "paper_2505_21013_amd", "read_bw")
+        if not os.path.exists(exe):
+            sys.exit(f"{exe} is not built (python -c 'import __graft_entry__ as g; g.build()')")
+        sys.exit(subprocess.run([exe, str(a.read_bw_mib)]).returncode)
     if a.launch_gaps:
         # 12 and 5 us: the product and the update of one PCG iteration on the twisted beam
         exe = os.path.join(ROOT, "paper_2505_21013_amd", "launch_gaps")
